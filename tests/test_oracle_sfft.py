@@ -1,0 +1,274 @@
+"""Pins of the oracle's construction (Alg. 1), random streams, selection and sparse FFT driver
+(Alg. 3) against closed forms, published test vectors, brute force and the paper's printed
+statistics.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import rng as R
+from oracle import construct as C
+from oracle import mr1l as O
+from oracle import sfft as S
+from workloads import rng_for, distinct_freqs, random_planted, planted_c1, primes_between
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([int(v) for v in line.split()])
+    return rows
+
+
+# ---- random streams ------------------------------------------------------------------------------
+
+def test_splitmix64_published_vectors():
+    for row in _golden_rows("splitmix64.txt"):
+        seed, outs = row[0], row[1:]
+        assert [R.draw(seed, c) for c in range(len(outs))] == outs
+
+
+def test_uniform_int_unbiased_rejection():
+    k = R.key(5, R.Z, 1, 0, 1)
+    vals = []
+    c = 0
+    for _ in range(20000):
+        v, c = R.uniform_int(k, c, 7)
+        vals.append(v)
+    h = np.bincount(vals, minlength=7)
+    assert h.min() > 2600 and h.max() < 3100
+    # a modulus just above 2^63 rejects about half of the draws; the counter must advance past them
+    v, c2 = R.uniform_int(k, 0, (1 << 63) + 1)
+    assert c2 >= 1 and 0 <= v <= (1 << 63)
+
+
+def test_gaussian_noise_moments():
+    g = np.arange(200000)
+    eta = R.gaussian_noise(123, 1, 2, 3, g, 0.5)
+    assert abs(np.mean(np.abs(eta) ** 2) - 0.25) < 0.01          # E|eta|^2 = sigma^2 (Sec. 5.2)
+    assert abs(np.mean(eta.real)) < 0.01 and abs(np.mean(eta.imag)) < 0.01
+    assert abs(np.var(eta.real) - 0.125) < 0.005 and abs(np.var(eta.imag) - 0.125) < 0.005
+    # Gaussian tails: P(|Re| > 2 sd) ~ 4.55 %
+    frac = np.mean(np.abs(eta.real) > 2 * math.sqrt(0.125))
+    assert abs(frac - 0.0455) < 0.004
+
+
+# ---- Alg. 1 --------------------------------------------------------------------------------------
+
+def test_lmax_lambda_closed_forms():
+    # c = 2, gamma = 1/2: L_max = ceil(2 ln(2|I|)), lambda = 2(|I| - 1)
+    for n in (1, 2, 17, 850, 65000, 1 << 16):
+        assert C.lmax(n, 2.0, 0.5) == math.ceil(2 * math.log(2 * n) - 1e-12)
+        assert C.lam(n, 2.0) == 2 * (n - 1)
+    assert C.lmax(850) == 15
+    assert C.lmax(65000) == 24
+    assert C.lmax(1000, c=3.0, gamma=0.1) == math.ceil(9 / 4 * (math.log(1000) + math.log(10)) / 2)
+
+
+def test_prime_sizes_golden_and_sieve():
+    f = distinct_freqs(rng_for(200), 850, 5, -8, 8)
+    got = C.prime_sizes(f, C.lam(850), 15)
+    assert got == _golden_rows("primes_after_1698.txt")[0]
+    sieve = primes_between(100000, 101000)
+    f2 = distinct_freqs(rng_for(201), 10, 2, -3, 3)
+    assert C.prime_sizes(f2, 99999.5, len(sieve)) == sieve.tolist()
+
+
+def test_prime_sizes_skip_non_injective():
+    # I = {0, 7}: lambda = 2, L_max = 3; 7 divides 7 - 0 so p = 7 is not in P^I
+    f = np.array([[0], [7]], np.int32)
+    assert C.prime_sizes(f, C.lam(2), 3) == [3, 5, 11]
+
+
+def test_construct_covers_by_definition():
+    f = distinct_freqs(rng_for(202), 300, 4, -10, 10)
+    M, z, covered, calls = C.construct_retry(f, b=10, seed=77, t=3)
+    assert covered and calls >= 1
+    assert len(set(M.tolist())) == len(M)                       # distinct sizes
+    assert np.all(M > C.lam(300)) and len(M) <= C.lmax(300)
+    uniq, counter = O.unaliased_sets_pairwise(f[:300], M, z)
+    assert counter.min() >= 1                                    # union of I_l is I
+    assert np.all((z >= 0) & (z < M[:, None]))
+
+
+def test_construct_deterministic_and_keyed():
+    f = distinct_freqs(rng_for(203), 120, 3, -5, 5)
+    a = C.construct(f, seed=1, t=2, attempt=0)
+    b = C.construct(f, seed=1, t=2, attempt=0)
+    c = C.construct(f, seed=1, t=2, attempt=1)
+    assert np.array_equal(a[1], b[1])
+    assert not np.array_equal(a[1][0], c[1][0])
+
+
+def test_construct_lattice_count_statistics():
+    """Expected number of lattices: each new lattice leaves a fixed k aliased with probability
+    about 1 - (1 - 1/M)^(n-1) ~ 1 - e^{-1/2} (M ~ 2n); L ~ ln n / -ln(1 - e^{-1/2})."""
+    f = distinct_freqs(rng_for(204), 2000, 6, -20, 20)
+    Ls = [len(C.construct(f, seed=s, t=1)[0]) for s in range(6)]
+    expect = math.log(2000) / -math.log(1 - math.exp(-0.5))
+    assert abs(np.mean(Ls) - expect) < 3.0
+    assert max(Ls) <= C.lmax(2000)
+
+
+def test_parameter_rules():
+    assert C.b_rule(5, 0.01) == math.ceil((math.log(3) + math.log(5) + math.log(100)) / math.log(2))
+    assert C.b_rule_r1(20, 1e-3) == math.ceil(math.log(20e3) / math.log(2))
+    assert C.r_rule(10, 5, 0.1) == math.ceil(20 * (math.log(3) + math.log(5) + math.log(10) + math.log(10)))
+    # sample bound of Sec. 3.2 with r = 1, s = 50, N = 8
+    Lt = math.ceil(2 * math.log(850) + 2 * math.log(2))
+    assert C.sample_bound(1, 50, 8) == 2 * Lt * max(2 * 849, 4 * Lt * math.log(Lt))
+
+
+# ---- selection -----------------------------------------------------------------------------------
+
+def test_select_top_bruteforce_with_ties():
+    rng = rng_for(205)
+    for trial in range(50):
+        n = int(rng.integers(1, 40))
+        mags = rng.choice([0.0, 0.5, 1.0, 2.0, 3.0], size=n)
+        vals = mags * np.exp(2j * np.pi * rng.choice([0.0, 0.25, 0.5], size=n))
+        delta, s = 0.9, int(rng.integers(1, 8))
+        got = S.select_top(vals, delta, s).tolist()
+        keyed = [(-(v.real * v.real + v.imag * v.imag), i) for i, v in enumerate(vals)
+                 if v.real * v.real + v.imag * v.imag >= delta * delta]
+        ref = sorted(i for _, i in sorted(keyed)[:s])
+        assert got == ref
+
+
+# ---- Alg. 3 building blocks ----------------------------------------------------------------------
+
+def _poly(seed, d=4, N=5, s=30, mag="unit"):
+    return random_planted(rng_for(206, seed), d, N, s, mag)
+
+
+def test_sampler_tier1_matches_direct():
+    p = _poly(0)
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+    f3 = np.unique(p.freqs[:, :3], axis=0)
+    M, z, _, _ = C.construct_retry(f3, 10, seed=3, t=3)
+    tail = np.array([0.3, 0.71])[: p.d - 3]
+    y1 = bb.sample_lattice(3, 1, M, z, tail, tier=1)
+    y0 = bb.sample_lattice(3, 1, M, z, tail, tier=0)
+    assert np.abs(y1 - y0).max() < 1e-11
+
+
+def test_projected_coefficients_closed_form():
+    """Sec. 4.1: with a reconstructing lattice for J_t, Alg. 2 on the lattice samples returns
+    sum_{h : h_{1..t} = k} c_h e^{2 pi i h_{t+1..d} . x~} for every k in J_t."""
+    p = _poly(1, d=5, N=4, s=40)
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+    t = 3
+    proj = np.unique(p.freqs[:, :t], axis=0)
+    extra = distinct_freqs(rng_for(207), 30, t, -4, 4)
+    J = np.unique(np.concatenate([proj, extra]), axis=0)
+    M, z, covered, _ = C.construct_retry(J, 10, seed=9, t=t)
+    assert covered
+    tail = np.array([0.123, 0.456])
+    got = O.forward(J, M, z, bb.sample_lattice(t, 1, M, z, tail))
+    ref = np.zeros(len(J), np.complex128)
+    w = p.coeffs * np.exp(2j * np.pi * (p.freqs[:, t:] @ tail))
+    index = {tuple(k): a for a, k in enumerate(J.tolist())}
+    for h, wh in zip(p.freqs[:, :t].tolist(), w):
+        ref[index[tuple(h)]] += wh
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_one_dim_aliasing_formula():
+    """eq. for the 1-D projections (Sec. 4.1): with K_t >= the box width, p~_{t,k} equals
+    sum_{h : h_t = k} c_h e^{2 pi i (h without component t) . x'} (factor 1/K_t, reading R1)."""
+    p = _poly(2, d=4, N=6, s=25)
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+    anchors = np.array([0.11, 0.52, 0.93, 0.34])
+    t = 2
+    y = bb.sample_1d(t, 1, anchors, 13)
+    got = S.projection_1d(y, -6, 6)
+    other = [0, 2, 3]
+    ref = np.zeros(13, np.complex128)
+    for h, c in zip(p.freqs, p.coeffs):
+        ref[h[t - 1] + 6] += c * np.exp(2j * np.pi * (h[other] @ anchors[other]))
+    assert np.abs(got - ref).max() < 1e-12
+
+
+# ---- Alg. 3 end to end ---------------------------------------------------------------------------
+
+def _sorted(f):
+    return f[np.lexsort(f.T[::-1])]
+
+
+def test_sfft_recovers_planted_c1_tiers_agree():
+    """Noise-free unit-modulus polynomial, r = 1, delta = 1e-12: the output is supp p with
+    coefficient errors at machine precision (Table 5.1 reports 2e-16 .. 1.3e-15)."""
+    p = planted_c1()
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+    res = S.sfft(p.lo, p.hi, bb, 1e-12, 50, 50, r=1, b=10, seed=1711051520)
+    order = np.lexsort(p.freqs.T[::-1])
+    assert np.array_equal(res.freqs, p.freqs[order])
+    err = np.linalg.norm(res.coeffs - p.coeffs[order]) / np.linalg.norm(p.coeffs)
+    assert err < 1e-14
+
+
+def test_sfft_tier0_equals_tier1_small():
+    p = random_planted(rng_for(208), 3, 3, 8, "unit")
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+    r1 = S.sfft(p.lo, p.hi, bb, 1e-10, 8, 8, r=2, b=5, seed=4, tier=1)
+    r0 = S.sfft(p.lo, p.hi, bb, 1e-10, 8, 8, r=2, b=5, seed=4, tier=0)
+    assert np.array_equal(r1.freqs, r0.freqs)
+    assert np.abs(r1.coeffs - r0.coeffs).max() < 1e-11
+    assert np.array_equal(r1.freqs, _sorted(p.freqs))
+
+
+def test_sfft_no_false_positives_with_larger_s():
+    """Sec. 4.1: with Gamma containing the support, detected frequencies are in supp p even when
+    s exceeds the sparsity (thresholding removes the empty candidates)."""
+    p = random_planted(rng_for(209), 4, 4, 20, "u1_10")
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+    res = S.sfft(p.lo, p.hi, bb, 1e-6, 500, 500, r=2, b=10, seed=5)
+    assert np.array_equal(res.freqs, _sorted(p.freqs))
+
+
+def test_sfft_empty_signal_and_d1():
+    bb = S.PlantedBlackBox(np.zeros((0, 3), np.int32), np.zeros(0))
+    res = S.sfft([-2] * 3, [2] * 3, bb, 1e-9, 5, 5, r=1, b=3, seed=1)
+    assert res.freqs.shape == (0, 3)
+    p = random_planted(rng_for(210), 1, 10, 4, "unit")
+    bb1 = S.PlantedBlackBox(p.freqs, p.coeffs)
+    res1 = S.sfft(p.lo, p.hi, bb1, 1e-9, 4, 4, r=1, b=3, seed=1)
+    order = np.argsort(p.freqs[:, 0])
+    assert np.array_equal(res1.freqs, p.freqs[order])
+    assert np.abs(res1.coeffs - p.coeffs[order]).max() < 1e-13
+
+
+def test_sfft_noisy_recovery():
+    """Sec. 5.2 noise model: moderate noise still yields the support with r = 2."""
+    p = random_planted(rng_for(211), 4, 6, 30, "unit", sigma=1e-2, noise_seed=99)
+    bb = S.PlantedBlackBox(p.freqs, p.coeffs, p.sigma, p.noise_seed)
+    res = S.sfft(p.lo, p.hi, bb, 0.2, 30, 30, r=2, b=10, seed=6)
+    order = np.lexsort(p.freqs.T[::-1])
+    assert np.array_equal(res.freqs, p.freqs[order])
+    assert np.abs(res.coeffs - p.coeffs[order]).max() < 1e-2
+
+
+@pytest.mark.slow
+def test_sample_count_matches_table_5_1():
+    """Ex. 5.1 / Table 5.1 (d = 5, N = 32, s = 1000, r = 1, delta = 1e-12, coefficients in
+    [-1,1)+[-1,1)i): the paper's MLFFT column prints a maximum of 4,525,799 samples over 10 runs
+    and a maximal relative l2 error of 5.3e-16 (Fig. 5.1a prints 4,647,753 for the same
+    setting).  Ten seeded runs: all recover the support, the maximum sample count lies within
+    15 % of the printed one and the errors are at machine precision."""
+    gold = dict(tuple(r) for r in _golden_rows("table51_mlfft_samples.txt"))
+    counts, errs = [], []
+    for rep in range(10):
+        p = random_planted(rng_for(212, rep), 5, 32, 1000, "box")
+        bb = S.PlantedBlackBox(p.freqs, p.coeffs)
+        res = S.sfft(p.lo, p.hi, bb, 1e-12, 1000, 1000, r=1, b=10, seed=8 + rep)
+        order = np.lexsort(p.freqs.T[::-1])
+        assert np.array_equal(res.freqs, p.freqs[order])
+        errs.append(np.linalg.norm(res.coeffs - p.coeffs[order]) / np.linalg.norm(p.coeffs))
+        counts.append(res.samples)
+    assert max(errs) < 2e-15
+    assert abs(max(counts) - gold[5]) <= 0.15 * gold[5], counts
