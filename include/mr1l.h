@@ -1,0 +1,209 @@
+/*
+ * mr1l.h -- C ABI of the MI355X multiple rank-1 lattice FFT and the dimension-incremental sparse
+ * FFT built on it (Kaemmerer, Potts, Volkmer, "High-dimensional sparse FFT based on sampling along
+ * multiple rank-1 lattices", arXiv 1711.05152).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Frequencies are int32 rows k in Z^d, row-major [n][d], host memory.
+ * - A multiple rank-1 lattice is L pairs (M_l, z_l), M_l >= 1, z_l in Z^d (any integers; they are
+ *   reduced modulo M_l).  Its samples are stored lattice after lattice: lattice l owns entries
+ *   [off_l, off_l + M_l) of a vector of length sum_l M_l, and entry j of that slice is the value
+ *   at the node (j z_l / M_l) mod 1 (definition of Lambda(z, M), Sec. 2.1).
+ * - Complex data are interleaved (re, im) pairs: MR1L_C64 = two floats, MR1L_C128 = two doubles.
+ *   Multi right-hand-side data are [n_rhs][...] with the rhs index slowest.
+ * - Device pointers are HIP device memory on the plan's device; ``stream`` is a hipStream_t (or
+ *   NULL for the default stream).  Transform calls only enqueue work on that stream and return;
+ *   they never synchronize.  The caller owns every buffer passed in.
+ * - Every entry point returns a status and never aborts.  Arguments are validated before any
+ *   work is enqueued; on error nothing is launched and mr1l_last_error() describes the problem
+ *   (thread-local, valid until the next call on the same thread).
+ * - A plan is bound to one device and must not be used by two host threads at once; calls on
+ *   one plan must be ordered on one stream (the plan owns one scratch area).
+ */
+#ifndef MR1L_H
+#define MR1L_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mr1l_status {
+    MR1L_OK = 0,
+    MR1L_ERR_ARG = 1,          /* invalid argument (sizes, pointers, duplicate frequencies ...) */
+    MR1L_ERR_OVERFLOW = 2,     /* d * max|k| * max M_l too large for exact int64 residues      */
+    MR1L_ERR_NOMEM = 3,        /* device or host allocation failed                              */
+    MR1L_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed                    */
+    MR1L_ERR_CALLBACK = 5,     /* the user sampler returned non-zero                            */
+    MR1L_ERR_UNSUPPORTED = 6,  /* valid but outside this build's limits (e.g. M_l >= 2^31)      */
+    MR1L_WARN_UNCOVERED = 16   /* result defined, but some frequency lies in no I_l            */
+} mr1l_status;
+
+typedef enum mr1l_dtype { MR1L_C64 = 0, MR1L_C128 = 1 } mr1l_dtype;
+
+/* Weighting of the transform pair.
+ * MR1L_W_PAPER -- Alg. 2 (inverse multiple rank-1 lattice FFT):
+ *   forward  c_k = (1/counter_k) sum_{l: k in I_l} (1/M_l) sum_j y_l[j] e^{-2 pi i j (k.z_l)/M_l}
+ *            with I_l = { k in I : no h != k in I has h.z_l = k.z_l (mod M_l) } and
+ *            counter_k = #{l : k in I_l};  c_k = 0 when counter_k = 0.
+ *   adjoint  y_l[j] = (1/M_l) sum_{k in I_l} (c_k/counter_k) e^{+2 pi i j (k.z_l)/M_l}
+ *            (the exact adjoint of the forward map).
+ * MR1L_W_EVAL -- the Fourier matrix A(X, I) = (e^{2 pi i k.x})_{x in X, k in I} of Sec. 2.1 on the
+ *   stacked lattice nodes:  adjoint computes y = A c (synthesis, every k, colliding residues
+ *   summed), forward computes A^* y = sum_l DFT_{M_l}(y_l)[k.z_l mod M_l] (no 1/M_l, every l). */
+typedef enum mr1l_weights { MR1L_W_PAPER = 0, MR1L_W_EVAL = 1 } mr1l_weights;
+
+typedef struct mr1l_plan_s* mr1l_plan_t;
+
+/* Build a transform plan (Alg. 2, inputs I and Lambda; Sec. 2.1 for the lattice definition).
+ *   d, n        dimension (1..64) and number of frequencies (n >= 0)
+ *   freqs       host int32 [n][d], pairwise distinct rows (checked)
+ *   L, M, z     host int64 [L] lattice sizes (1 <= M_l < 2^31) and [L][d] generating vectors
+ *   dtype       precision of samples, coefficients and arithmetic
+ *   weights     MR1L_W_PAPER or MR1L_W_EVAL (see above)
+ *   n_rhs       number of right-hand sides transformed per call (>= 1)
+ *   device      HIP device index the plan lives on
+ *   out         receives the plan; released with mr1l_destroy
+ * The plan allocates its device scratch (packed frequencies, alias bitmaps, Bluestein filter
+ * spectra, work area) and computes the filter spectra on the device; it synchronizes the device
+ * before returning.  Errors: MR1L_ERR_ARG (bad sizes/pointers, duplicate rows),
+ * MR1L_ERR_OVERFLOW (d * max|k| * max M_l >= 2^52), MR1L_ERR_UNSUPPORTED (M_l >= 2^31),
+ * MR1L_ERR_NOMEM, MR1L_ERR_HIP. */
+mr1l_status mr1l_plan(int d, int64_t n, const int32_t* freqs, int L, const int64_t* M,
+                      const int64_t* z, mr1l_dtype dtype, mr1l_weights weights, int64_t n_rhs,
+                      int device, mr1l_plan_t* out);
+
+/* Forward transform (Alg. 2; the residues k.z_l mod M_l, the alias histograms, the prime-length
+ * DFTs and the gather are all recomputed on every call).
+ *   samples  device [n_rhs][sum_l M_l] complex (read only)
+ *   coeffs   device [n_rhs][n] complex (written)
+ * Asynchronous on ``stream``. */
+mr1l_status mr1l_forward(mr1l_plan_t plan, const void* samples, void* coeffs, void* stream);
+
+/* Adjoint transform (the adjoint of the forward map, see mr1l_weights).
+ *   coeffs   device [n_rhs][n] complex (read only)
+ *   samples  device [n_rhs][sum_l M_l] complex (written)
+ * Asynchronous on ``stream``. */
+mr1l_status mr1l_adjoint(mr1l_plan_t plan, const void* coeffs, void* samples, void* stream);
+
+/* Integer outputs of the residue and alias-histogram passes (Alg. 1 and Alg. 2, definition of
+ * I_l and counter), for inspection and exact comparison.  Any output may be NULL.
+ *   residues   device int64 [L][n]: k.z_l mod M_l in [0, M_l)
+ *   unaliased  device uint8 [L][n]: 1 iff k is in I_l
+ *   counter    device uint8 [n]: #{l : k in I_l} (saturates at 255)
+ * Asynchronous on ``stream``. */
+mr1l_status mr1l_alias(mr1l_plan_t plan, int64_t* residues, uint8_t* unaliased, uint8_t* counter,
+                       void* stream);
+
+/* Host-side facts about the plan (synchronous).  Any output may be NULL.
+ *   sample_offsets  host int64 [L+1]: off_l, off_L = sum_l M_l
+ *   n_uncovered     number of frequencies with counter 0 (reading of Alg. 2 for that case: c_k = 0)
+ *   fft_lengths     host int64 [L]: Bluestein convolution length used for lattice l */
+mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_uncovered,
+                      int64_t* fft_lengths);
+
+/* Release a plan and its device memory (NULL is accepted). */
+mr1l_status mr1l_destroy(mr1l_plan_t plan);
+
+/* Per-stage device timing.  While enabled, every forward/adjoint call records HIP events on its
+ * stream around each kernel stage; mr1l_timing_read returns the summed milliseconds and launch
+ * counts per stage and resets them (it synchronizes the events it reads).
+ *   names      optional host array of MR1L_NSTAGES C strings receiving the stage names */
+#define MR1L_NSTAGES 8
+mr1l_status mr1l_timing_enable(mr1l_plan_t plan, int enable);
+mr1l_status mr1l_timing_read(mr1l_plan_t plan, double* ms_sum, int64_t* launches,
+                             const char** names);
+
+/* Alg. 1: randomized construction of a reconstructing multiple rank-1 lattice with pairwise
+ * distinct prime sizes, called until every k lies in some I_l, at most b calls (Alg. 3 step 2b).
+ *   d, n, freqs   host int32 [n][d] frequency set (distinct rows)
+ *   c, gamma      oversampling factor c > 1 and failure-probability bound 0 < gamma < 1
+ *   b             maximal number of Alg. 1 calls (>= 1); the last call is kept if none covers I
+ *   seed, t       key of the generating-vector stream (SplitMix64, fields (t, call, L))
+ *   L_cap         capacity of M and z (L_max = ceil(c^2/(c-1)^2 (ln n - ln gamma)/2) suffices)
+ *   L_out         number of lattices returned
+ *   M, z          host int64 [L_cap] sizes and [L_cap][d] generating vectors
+ *   calls         number of Alg. 1 calls made
+ *   n_uncovered   frequencies in no I_l (0 on success)
+ *   device        device the residue/alias passes run on (synchronous)
+ * Returns MR1L_WARN_UNCOVERED when b calls did not cover I (outputs still valid). */
+mr1l_status mr1l_construct(int d, int64_t n, const int32_t* freqs, double c, double gamma, int b,
+                           uint64_t seed, int64_t t, int L_cap, int* L_out, int64_t* M,
+                           int64_t* z, int* calls, int64_t* n_uncovered, int device);
+
+/* ---- dimension-incremental sparse FFT (Alg. 3) ------------------------------------------------ */
+
+/* Black box p(x) given by the caller: fill values_dev[j] = p(nodes_dev[j]) for j < n_nodes.
+ * nodes_dev is device double [n_nodes][d] with coordinates in [0,1); values_dev is device complex
+ * in the run's dtype.  Enqueue on ``stream`` or finish before returning; return 0 on success. */
+typedef int (*sfft_sampler_fn)(void* user, int d, int64_t n_nodes, const double* nodes_dev,
+                               void* values_dev, void* stream);
+
+/* Built-in black box: a planted sparse polynomial p(x) = sum_h c_h e^{2 pi i h.x} plus complex
+ * Gaussian noise eta = sigma/sqrt(2) (N(0,1) + i N(0,1)) on every sample (noise model of Sec. 5.2),
+ * drawn from a counter-based stream keyed by noise_seed. */
+typedef struct sfft_planted {
+    int64_t s;               /* number of terms                                  */
+    const int32_t* freqs;    /* host int32 [s][d]                                */
+    const double* coeffs;    /* host double [s][2] (re, im)                      */
+    double sigma;            /* noise level (0 = exact samples)                  */
+    uint64_t noise_seed;
+} sfft_planted;
+
+typedef struct sfft_params {
+    double delta;            /* absolute threshold                               */
+    int64_t s;               /* sparsity of the output                           */
+    int64_t s_local;         /* sparsity of intermediate steps (0: use s)        */
+    int r;                   /* detection iterations                             */
+    int b;                   /* maximal Alg. 1 calls per step                    */
+    uint64_t seed;           /* key of the generating-vector and anchor streams  */
+    mr1l_dtype dtype;        /* precision of the transforms                      */
+    double c, gamma;         /* Alg. 1 parameters (0 selects 2 and 1/2)          */
+    int zero_anchors;        /* 1: anchors fixed to 0 (r = 1 mode of Sec. 3.1)   */
+} sfft_params;
+
+#define SFFT_MAX_D 64
+typedef struct sfft_stats {
+    int d;
+    int64_t n_It[SFFT_MAX_D];      /* |I^(t)|                                          */
+    int64_t n_J[SFFT_MAX_D];       /* |J_t| = |I^(1..t-1) x I^(t)| (t >= 2)           */
+    int64_t n_detected[SFFT_MAX_D];/* |I^(1..t)|                                       */
+    int32_t L[SFFT_MAX_D];         /* lattices used at step t                          */
+    int64_t sumM[SFFT_MAX_D];      /* sum of their sizes                               */
+    int32_t calls[SFFT_MAX_D];     /* Alg. 1 calls at step t                           */
+    int64_t uncovered[SFFT_MAX_D]; /* frequencies of J_t in no I_l after the last call */
+    int64_t samples;               /* distinct nodes: sum r K_t + sum r~ (1 - L + sum M) */
+    int64_t samples_full;          /* values drawn (every lattice sampled in full)     */
+    double ms_sampling, ms_transform, ms_construct, ms_select, ms_total;
+} sfft_stats;
+
+/* Alg. 3 on the box search space Gamma = [lo_1, hi_1] x ... x [lo_d, hi_d].
+ *   d, lo, hi      host int32 [d] box corners (lo <= hi, hi - lo < 2^20)
+ *   sampler, user  caller's black box (used when planted == NULL)
+ *   planted        built-in black box (takes precedence over sampler when not NULL)
+ *   params         thresholds, sparsities, r, b, seed, dtype
+ *   cap            capacity of freqs_out / coeffs_out
+ *   n_out          number of detected frequencies (<= min(s, |Gamma|)); if it exceeds cap only
+ *                  the first cap are written and MR1L_ERR_ARG is returned
+ *   freqs_out      host int32 [cap][d], lexicographically ascending
+ *   coeffs_out     host double [cap][2] coefficients from the final transform
+ *   stats          optional per-step statistics
+ * Synchronous.  Returns MR1L_WARN_UNCOVERED when some step kept a non-reconstructing lattice. */
+mr1l_status sfft_detect(int d, const int32_t* lo, const int32_t* hi, sfft_sampler_fn sampler,
+                        void* user, const sfft_planted* planted, const sfft_params* params,
+                        int64_t cap, int64_t* n_out, int32_t* freqs_out, double* coeffs_out,
+                        sfft_stats* stats, int device);
+
+/* Thread-local description of the last error (empty string when none). */
+const char* mr1l_last_error(void);
+
+/* Library version string. */
+const char* mr1l_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MR1L_H */

@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libmr1l.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mr1l {
+
+// ---- complex arithmetic ---------------------------------------------------------------------------
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__host__ __device__ inline cx<T> make_cx(T a, T b) { return cx<T>{a, b}; }
+template <typename T>
+__device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ inline cx<T> cmul(cx<T> a, cx<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename T>
+__device__ inline cx<T> cmulc(cx<T> a, cx<T> b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a * conj(b)
+template <typename T>
+__device__ inline cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ inline cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+
+// e^{i pi x} from an exactly representable argument (x given in double).
+__device__ inline void sincospi_d(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// ---- lattice descriptors ---------------------------------------------------------------------------
+// One entry per rank-1 lattice of a transform.  All offsets are in elements.
+struct LatDesc {
+    int64_t M;         // lattice size M_l
+    int64_t samp_off;  // first sample of lattice l inside one right-hand side
+    int64_t work_off;  // first element of its Bluestein work region (length 2^lgN) per rhs
+    int64_t filt_off;  // first element of its filter spectrum (length 2^lgN)
+    int64_t bm_off;    // first 32-bit word of its alias bitmaps: seen [bm_words] then multi [bm_words]
+    int64_t bm_words;  // ceil(M / 32)
+    int64_t zoff;      // first component of z_l in the generating-vector table
+    double invM;       // 1 / M
+    int32_t lgN;       // Bluestein length 2^lgN >= 2M - 1
+    int32_t lgN1;      // four-step split: 2^lgN = 2^lgN1 * 2^lgN2 (lgN1 = 0 on the one-block path)
+    int32_t lgN2;
+    int32_t small;     // 1: the whole Bluestein convolution runs in one workgroup
+};
+
+// One entry per independent transform of a plan (a plain plan has one; a batched plan many).
+// Its frequencies are [foff, foff + fn) of the plan's frequency table and of every coefficient
+// vector; its lattices are [lat0, lat0 + nlat) of the descriptor table.
+struct TxDesc {
+    int64_t foff;
+    int64_t fn;
+    int32_t lat0;
+    int32_t nlat;
+};
+
+// Frequencies are kept component-major (structure of arrays) in the narrowest signed integer
+// type that holds them.
+enum KType { K_I8 = 0, K_I16 = 1, K_I32 = 2 };
+
+constexpr int kThreads = 256;      // threads per workgroup of every FFT kernel
+constexpr int kSmallMaxLg = 12;    // one-block Bluestein up to 2^12 points
+constexpr int kTwLg = 12;          // twiddle table e^{-2 pi i m / 4096}, m < 4096
+
+// Elements held in LDS by one four-step tile (fp32: 64 KiB, fp64: 64 KiB).
+template <typename T> struct TileElems;
+template <> struct TileElems<float> { static constexpr int lg = 13; };
+template <> struct TileElems<double> { static constexpr int lg = 12; };
+
+// ---- launchers (defined in the .hip files) ---------------------------------------------------------
+struct FreqView {
+    const void* f;   // component-major [d][nf]
+    int ktype;
+    int d;
+    int64_t nf;      // stride between components
+};
+
+// Transform launch context shared by the stage launchers.
+struct TxArgs {
+    const LatDesc* desc;      // device [L]
+    int L;
+    const TxDesc* tx;         // device [ntx]
+    const int64_t* tx_foff;   // device [ntx + 1] frequency prefix sums (binary search)
+    int ntx;
+    int max_nlat;             // largest lattice count of one transform
+    const int64_t* z;         // device generating vectors
+    FreqView fv;
+    int64_t n;                // frequencies of all transforms = coefficients per rhs
+    int64_t n_rhs;
+    int64_t samp_stride;      // elements per rhs in the sample vector
+    int64_t work_stride;      // elements per rhs in the work area
+    uint32_t* bitmaps;        // device alias bitmaps
+    int64_t bm_total;         // words of all bitmaps
+    // four-step tiling (large lattices)
+    const int* large;         // device [nlarge] lattice indices
+    const int* tile0_col;     // device [nlarge + 1] column-tile prefix sums
+    const int* tile0_row;     // device [nlarge + 1] row-tile prefix sums
+    int nlarge, tiles_col, tiles_row;
+    const int* small;         // device [nsmall] lattice indices
+    int nsmall;
+    bool fast_mod;            // residues may use the fp64 quotient estimate
+};
+
+template <typename T> const cx<T>* twiddles(int device);   // e^{-2 pi i m/4096}, m < 4096
+
+template <typename T>
+void launch_clear_u32(uint32_t* p, int64_t words, hipStream_t s);
+template <typename T>
+void launch_residue_hist(const TxArgs& a, hipStream_t s);
+template <typename T>
+void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval, hipStream_t s);
+template <typename T>
+void launch_clear_bins(const TxArgs& a, cx<T>* work, hipStream_t s);
+template <typename T>
+void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval, hipStream_t s);
+void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s);
+
+// Bluestein stages.  sign = -1: DFT with e^{-2 pi i jm/M} (forward), +1: with e^{+...} (adjoint).
+// Stage "in": chirped input from src (samples, or the bins already in the work area) into work.
+template <typename T>
+void launch_bluestein_small(const TxArgs& a, const cx<T>* src, int64_t src_stride, bool src_is_samples,
+                            cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
+                            bool dst_is_samples, int sign, bool scale_by_invM, hipStream_t s);
+template <typename T>
+void launch_p1(const TxArgs& a, const cx<T>* src, int64_t src_stride, bool src_is_samples, cx<T>* work,
+               int sign, hipStream_t s);
+template <typename T>
+void launch_p2(const TxArgs& a, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s);
+template <typename T>
+void launch_p3(const TxArgs& a, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
+               int sign, bool scale_by_invM, hipStream_t s);
+
+// Filter spectra: filt_l = DFT_{2^lgN}(b_l) / 2^lgN with b_l[n] = e^{+i pi n^2 / M_l} for |n| < M_l
+// (wrapped), stored in the layout stage 2 reads (natural order on the one-block path,
+// [k1][k2] = B[k1 + N1 k2] on the four-step path).
+template <typename T>
+void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cx<T>* filt, int64_t filt_total,
+                   int device, hipStream_t s);
+
+}  // namespace mr1l

@@ -1,0 +1,263 @@
+// Alg. 1: reconstructing multiple rank-1 lattices with pairwise distinct prime sizes, plus the
+// repetition of Alg. 3 step 2b (at most b calls, the last one kept if none covers I).
+//
+// Host side: L_max and lambda (Alg. 1 first two steps), the prime sizes p > lambda of P^I found by
+// trial division with a cached table of small primes, and the random generating vectors
+// (SplitMix64 Z stream keyed by (t, call, L)).  Device side: for every trial lattice the residues
+// of all frequencies, the alias bitmaps and the running union of the unaliased sets, followed by
+// one device-to-host copy of the number of covered frequencies (the stopping test of Alg. 1).
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "index_dev.h"
+#include "runtime.h"
+
+namespace mr1l {
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_trial_hist(const K* __restrict__ f, int64_t nf, int d, int64_t n,
+                                                    const int64_t* __restrict__ z, int64_t M, double invM, int fast,
+                                                    uint32_t* bm, int64_t words) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = dot_kz<K>(f, nf, d, g, z);
+        const int64_t r = fast ? mod_fast(s, M, invM) : mod_exact(s, M);
+        const uint32_t bit = 1u << (r & 31);
+        const uint32_t old = atomicOr(bm + (r >> 5), bit);
+        if (old & bit) atomicOr(bm + words + (r >> 5), bit);
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_trial_cover(const K* __restrict__ f, int64_t nf, int d, int64_t n,
+                                                     const int64_t* __restrict__ z, int64_t M, double invM, int fast,
+                                                     const uint32_t* __restrict__ bm, int64_t words, uint8_t* covered,
+                                                     unsigned long long* count) {
+    __shared__ unsigned int part[256];
+    unsigned int local = 0;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        if (covered[g]) {
+            ++local;
+            continue;
+        }
+        const int64_t s = dot_kz<K>(f, nf, d, g, z);
+        const int64_t r = fast ? mod_fast(s, M, invM) : mod_exact(s, M);
+        if (!((bm[words + (r >> 5)] >> (r & 31)) & 1u)) {
+            covered[g] = 1;
+            ++local;
+        }
+    }
+    part[threadIdx.x] = local;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(count, (unsigned long long)part[0]);
+}
+
+// any pair a < b with k_a = k_b componentwise mod p  ->  *found = 1
+template <typename K>
+__global__ void k_pairs_congruent(const K* __restrict__ f, int64_t nf, int d, int64_t n, int64_t p, int* found) {
+    const int64_t pairs = n * (n - 1) / 2;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < pairs; q += (int64_t)gridDim.x * blockDim.x) {
+        // row a of the strictly upper triangle: q = a n - a(a+1)/2 + (b - a - 1)
+        int64_t a = (int64_t)((2.0 * n - 1.0 - sqrt((2.0 * n - 1.0) * (2.0 * n - 1.0) - 8.0 * (double)q)) / 2.0);
+        if (a < 0) a = 0;
+        while (a > 0 && a * n - a * (a + 1) / 2 > q) --a;
+        while ((a + 1) * n - (a + 1) * (a + 2) / 2 <= q) ++a;
+        const int64_t b = q - (a * n - a * (a + 1) / 2) + a + 1;
+        bool same = true;
+        for (int c = 0; c < d && same; ++c) {
+            int64_t diff = (int64_t)f[c * nf + a] - (int64_t)f[c * nf + b];
+            same = (diff % p) == 0;
+        }
+        if (same) atomicOr(found, 1);
+    }
+}
+
+// ---- host helpers ----------------------------------------------------------------------------------
+static bool is_prime_u64(int64_t p) {
+    if (p < 2) return false;
+    if (p % 2 == 0) return p == 2;
+    for (int64_t q = 3; q * q <= p; q += 2)
+        if (p % q == 0) return false;
+    return true;
+}
+
+int64_t lmax_rule(int64_t n, double c, double gamma) {
+    return (int64_t)std::ceil(c * c / ((c - 1.0) * (c - 1.0)) * (std::log((double)n) - std::log(gamma)) / 2.0);
+}
+
+template <typename K>
+static mr1l_status congruent_pair_exists(const void* f, int64_t nf, int d, int64_t n, int64_t p, bool* out,
+                                         hipStream_t s) {
+    DevMem flag;
+    MR1L_HIP_TRY(flag.alloc(sizeof(int)));
+    MR1L_HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    const int64_t pairs = n * (n - 1) / 2;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(16384, (pairs + 255) / 256));
+    hipLaunchKernelGGL(k_pairs_congruent<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, nf, d, n, p,
+                       flag.as<int>());
+    MR1L_HIP_TRY(hipGetLastError());
+    int h = 0;
+    MR1L_HIP_TRY(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    MR1L_HIP_TRY(hipStreamSynchronize(s));
+    *out = h != 0;
+    return MR1L_OK;
+}
+
+template <typename K>
+static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, int64_t expansion, double c,
+                               double gamma, int b, uint64_t seed, int64_t t, hipStream_t s, ConstructResult* out) {
+    out->M.clear();
+    out->z.clear();
+    out->calls = 0;
+    out->uncovered = 0;
+    if (n == 0) return MR1L_OK;
+    const int64_t L_max = lmax_rule(n, c, gamma);
+    const double lambda = c * (double)(n - 1);
+
+    // P^I_{lambda, L_max}: the L_max smallest primes p > lambda with k -> k mod p injective on I
+    std::vector<int64_t> primes;
+    int64_t p = (int64_t)std::floor(lambda) + 1;
+    while ((int64_t)primes.size() < L_max) {
+        if (is_prime_u64(p)) {
+            bool ok = true;
+            if (p <= expansion) {   // otherwise distinct rows stay distinct modulo p
+                if (n > 65536) {
+                    set_error("prime-size injectivity check needs |I| <= 65536 when lambda < expansion of I");
+                    return MR1L_ERR_UNSUPPORTED;
+                }
+                bool clash = false;
+                mr1l_status st = congruent_pair_exists<K>(f, n, d, n, p, &clash, s);
+                if (st != MR1L_OK) return st;
+                ok = !clash;
+            }
+            if (ok) primes.push_back(p);
+        }
+        ++p;
+    }
+    const int64_t maxM = primes.back();
+    if (maxM >= ((int64_t)1 << 31)) {
+        set_error("lattice sizes beyond 2^31 are not supported");
+        return MR1L_ERR_UNSUPPORTED;
+    }
+    const long double bound = (long double)d * maxabs * maxM;
+    if (bound >= 0x1.0p62L) {
+        set_error("d * max|k| * max M >= 2^62");
+        return MR1L_ERR_OVERFLOW;
+    }
+    const int fast = bound < 0x1.0p52L;
+
+    DevMem bm, covered, count, zdev;
+    const int64_t words = (maxM + 31) / 32;
+    MR1L_HIP_TRY(bm.alloc(2 * words * sizeof(uint32_t)));
+    MR1L_HIP_TRY(covered.alloc((size_t)n));
+    MR1L_HIP_TRY(count.alloc(sizeof(unsigned long long)));
+    MR1L_HIP_TRY(zdev.alloc((size_t)d * sizeof(int64_t)));
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256));
+
+    std::vector<int64_t> zl(d);
+    for (int call = 0; call < std::max(1, b); ++call) {
+        out->M.clear();
+        out->z.clear();
+        out->calls = call + 1;
+        MR1L_HIP_TRY(hipMemsetAsync(covered.p, 0, (size_t)n, s));
+        unsigned long long ncov = 0;
+        for (int64_t L = 1; L <= L_max; ++L) {
+            const int64_t M = primes[L - 1];
+            const uint64_t key = Rng::key(seed, {Rng::Z, t, call, L});
+            uint64_t ctr = 0;
+            for (int i = 0; i < d; ++i) zl[i] = (int64_t)Rng::uniform_int(key, &ctr, (uint64_t)M);
+            out->M.push_back(M);
+            out->z.insert(out->z.end(), zl.begin(), zl.end());
+            const int64_t w = (M + 31) / 32;
+            MR1L_HIP_TRY(hipMemcpyAsync(zdev.p, zl.data(), d * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            MR1L_HIP_TRY(hipMemsetAsync(bm.p, 0, 2 * w * sizeof(uint32_t), s));
+            MR1L_HIP_TRY(hipMemsetAsync(count.p, 0, sizeof(unsigned long long), s));
+            hipLaunchKernelGGL(k_trial_hist<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
+                               zdev.as<int64_t>(), M, 1.0 / (double)M, fast, bm.as<uint32_t>(), w);
+            hipLaunchKernelGGL(k_trial_cover<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
+                               zdev.as<int64_t>(), M, 1.0 / (double)M, fast, (const uint32_t*)bm.p, w,
+                               covered.as<uint8_t>(), count.as<unsigned long long>());
+            MR1L_HIP_TRY(hipGetLastError());
+            MR1L_HIP_TRY(hipMemcpyAsync(&ncov, count.p, sizeof(ncov), hipMemcpyDeviceToHost, s));
+            MR1L_HIP_TRY(hipStreamSynchronize(s));
+            if ((int64_t)ncov == n) break;
+        }
+        out->uncovered = n - (int64_t)ncov;
+        if (out->uncovered == 0) break;
+    }
+    return MR1L_OK;
+}
+
+mr1l_status construct_lattices(int d, int64_t n, const int32_t* host_freqs, const void* dev_freqs, int ktype,
+                               int64_t maxabs, int64_t expansion, double c, double gamma, int b, uint64_t seed,
+                               int64_t t, int device, hipStream_t s, ConstructResult* out) {
+    MR1L_HIP_TRY(hipSetDevice(device));
+    DevMem packed;
+    const void* f = dev_freqs;
+    if (host_freqs) {
+        maxabs = 0;
+        expansion = 0;
+        for (int c0 = 0; c0 < d; ++c0) {
+            int64_t lo = INT64_MAX, hi = INT64_MIN;
+            for (int64_t g = 0; g < n; ++g) {
+                const int64_t v = host_freqs[g * d + c0];
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+                maxabs = std::max<int64_t>(maxabs, std::llabs(v));
+            }
+            if (n) expansion = std::max(expansion, hi - lo);
+        }
+        ktype = K_I32;
+        std::vector<int32_t> soa((size_t)n * d);
+        for (int64_t g = 0; g < n; ++g)
+            for (int c0 = 0; c0 < d; ++c0) soa[(size_t)c0 * n + g] = host_freqs[g * d + c0];
+        MR1L_HIP_TRY(packed.upload(soa.data(), soa.size() * sizeof(int32_t)));
+        f = packed.p;
+    }
+    switch (ktype) {
+        case K_I8: return construct_t<int8_t>(d, n, f, maxabs, expansion, c, gamma, b, seed, t, s, out);
+        case K_I16: return construct_t<int16_t>(d, n, f, maxabs, expansion, c, gamma, b, seed, t, s, out);
+        default: return construct_t<int32_t>(d, n, f, maxabs, expansion, c, gamma, b, seed, t, s, out);
+    }
+}
+
+}  // namespace mr1l
+
+using namespace mr1l;
+
+extern "C" mr1l_status mr1l_construct(int d, int64_t n, const int32_t* freqs, double c, double gamma, int b,
+                                      uint64_t seed, int64_t t, int L_cap, int* L_out, int64_t* M, int64_t* z,
+                                      int* calls, int64_t* n_uncovered, int device) {
+    try {
+        clear_error();
+        if (d < 1 || d > 64 || n < 0 || (n > 0 && !freqs) || !(c > 1.0) || !(gamma > 0.0 && gamma < 1.0) || b < 1 ||
+            !L_out || L_cap < 0 || (L_cap > 0 && (!M || !z))) {
+            set_error("invalid argument to mr1l_construct");
+            return MR1L_ERR_ARG;
+        }
+        ConstructResult r;
+        mr1l_status st = construct_lattices(d, n, freqs, nullptr, K_I32, 0, 0, c, gamma, b, seed, t, device,
+                                            nullptr, &r);
+        if (st != MR1L_OK) return st;
+        const int L = (int)r.M.size();
+        *L_out = L;
+        if (calls) *calls = r.calls;
+        if (n_uncovered) *n_uncovered = r.uncovered;
+        if (L > L_cap) {
+            set_error("L_cap too small: need " + std::to_string(L));
+            return MR1L_ERR_ARG;
+        }
+        std::copy(r.M.begin(), r.M.end(), M);
+        std::copy(r.z.begin(), r.z.end(), z);
+        return r.uncovered ? MR1L_WARN_UNCOVERED : MR1L_OK;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return MR1L_ERR_ARG;
+    }
+}

@@ -1,0 +1,532 @@
+// Plans and the transform entry points of libmr1l (Alg. 2 and its adjoint).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+
+#include "runtime.h"
+
+namespace mr1l {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+static const char* kStageNames[MR1L_NSTAGES] = {"alias_hist", "bluestein_small", "bluestein_p1", "bluestein_p2",
+                                                "bluestein_p3", "gather",        "scatter",      "unused"};
+
+Plan::~Plan() {
+    for (auto& r : pending) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : free_events) hipEventDestroy(e);
+}
+
+static int ceil_lg(int64_t v) {
+    int lg = 0;
+    while (((int64_t)1 << lg) < v) ++lg;
+    return lg;
+}
+
+template <typename T>
+static int tile_lg() { return TileElems<T>::lg; }
+
+static mr1l_status check_distinct_rows(const int32_t* f, int64_t n, int d) {
+    std::vector<int64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        return std::lexicographical_compare(f + a * d, f + a * d + d, f + b * d, f + b * d + d);
+    });
+    for (int64_t i = 1; i < n; ++i)
+        if (std::equal(f + idx[i - 1] * d, f + idx[i - 1] * d + d, f + idx[i] * d)) {
+            set_error("frequency rows " + std::to_string(idx[i - 1]) + " and " + std::to_string(idx[i]) +
+                      " are equal");
+            return MR1L_ERR_ARG;
+        }
+    return MR1L_OK;
+}
+
+template <typename K>
+static void pack_soa(const int32_t* f, int64_t n, int d, std::vector<char>& out) {
+    out.resize((size_t)n * d * sizeof(K));
+    K* o = (K*)out.data();
+    for (int64_t g = 0; g < n; ++g)
+        for (int c = 0; c < d; ++c) o[(size_t)c * n + g] = (K)f[g * d + c];
+}
+
+template <typename T>
+static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
+    auto P = new Plan();
+    std::unique_ptr<Plan> guard(P);
+    P->device = sp.device;
+    P->d = sp.d;
+    P->dtype = sp.dtype;
+    P->weights = sp.weights;
+    P->n_rhs = sp.n_rhs;
+    const int d = sp.d;
+    const int ntx = (int)sp.tx_n.size();
+    int64_t n = 0;
+    int L = 0;
+    for (int i = 0; i < ntx; ++i) {
+        n += sp.tx_n[i];
+        L += sp.tx_L[i];
+    }
+    P->n = n;
+    P->L = L;
+    MR1L_HIP_TRY(hipSetDevice(sp.device));
+
+    // ---- frequencies ----
+    int64_t maxabs = 0;
+    int ktype = K_I32;
+    if (sp.host_freqs) {
+        for (int64_t i = 0; i < n * d; ++i) maxabs = std::max<int64_t>(maxabs, std::llabs((int64_t)sp.host_freqs[i]));
+        if (sp.check_distinct) {
+            int64_t off = 0;
+            for (int i = 0; i < ntx; ++i) {
+                mr1l_status st = check_distinct_rows(sp.host_freqs + off * d, sp.tx_n[i], d);
+                if (st != MR1L_OK) return st;
+                off += sp.tx_n[i];
+            }
+        }
+        ktype = maxabs <= 127 ? K_I8 : (maxabs <= 32767 ? K_I16 : K_I32);
+        std::vector<char> packed;
+        if (ktype == K_I8) pack_soa<int8_t>(sp.host_freqs, n, d, packed);
+        else if (ktype == K_I16) pack_soa<int16_t>(sp.host_freqs, n, d, packed);
+        else pack_soa<int32_t>(sp.host_freqs, n, d, packed);
+        MR1L_HIP_TRY(P->freqs.upload(packed.data(), packed.size()));
+        P->args.fv.f = P->freqs.p;
+    } else {
+        ktype = sp.dev_ktype;
+        maxabs = sp.dev_maxabs;
+        P->args.fv.f = sp.dev_freqs;
+    }
+    P->args.fv.ktype = ktype;
+    P->args.fv.d = d;
+    P->args.fv.nf = n;
+
+    // ---- lattices ----
+    int64_t maxM = 1;
+    std::vector<int64_t> zred((size_t)L * d);
+    for (int l = 0; l < L; ++l) {
+        const int64_t M = sp.M[l];
+        if (M < 1) {
+            set_error("lattice size M must be >= 1");
+            return MR1L_ERR_ARG;
+        }
+        if (M >= ((int64_t)1 << 23)) {
+            set_error("lattice size " + std::to_string(M) + " exceeds the supported maximum 2^23 - 1");
+            return MR1L_ERR_UNSUPPORTED;
+        }
+        maxM = std::max(maxM, M);
+        for (int c = 0; c < d; ++c) {
+            int64_t v = sp.z[(size_t)l * d + c] % M;
+            if (v < 0) v += M;
+            zred[(size_t)l * d + c] = v;
+        }
+    }
+    const long double bound = (long double)d * (long double)maxabs * (long double)maxM;
+    if (bound >= 0x1.0p62L) {
+        set_error("d * max|k| * max M >= 2^62: residues would overflow int64");
+        return MR1L_ERR_OVERFLOW;
+    }
+    P->args.fast_mod = bound < 0x1.0p52L;
+
+    P->hdesc.resize(L);
+    P->samp_off.assign(L + 1, 0);
+    int64_t woff = 0, bmoff = 0;
+    std::vector<int> smalls, larges, t0c, t0r;
+    int tc = 0, tr = 0;
+    const int LGE = tile_lg<T>();
+    for (int l = 0; l < L; ++l) {
+        LatDesc& D = P->hdesc[l];
+        D.M = sp.M[l];
+        D.invM = 1.0 / (double)D.M;
+        D.samp_off = P->samp_off[l];
+        P->samp_off[l + 1] = P->samp_off[l] + D.M;
+        D.lgN = ceil_lg(2 * D.M - 1);
+        D.small = D.lgN <= kSmallMaxLg;
+        D.lgN1 = D.small ? 0 : D.lgN / 2;
+        D.lgN2 = D.lgN - D.lgN1;
+        D.work_off = woff;
+        D.filt_off = woff;
+        woff += (int64_t)1 << D.lgN;
+        D.bm_words = (D.M + 31) / 32;
+        D.bm_off = bmoff;
+        bmoff += 2 * D.bm_words;
+        D.zoff = (int64_t)l * d;
+        if (D.small) {
+            smalls.push_back(l);
+        } else {
+            larges.push_back(l);
+            t0c.push_back(tc);
+            t0r.push_back(tr);
+            const int lgC = std::min(D.lgN2, LGE - D.lgN1);
+            const int lgR = std::min(D.lgN1, LGE - D.lgN2);
+            tc += 1 << (D.lgN2 - lgC);
+            tr += 1 << (D.lgN1 - lgR);
+        }
+    }
+    t0c.push_back(tc);
+    t0r.push_back(tr);
+    P->sum_M = P->samp_off[L];
+    P->work_stride = woff;
+    P->filt_total = woff;
+    P->bm_total = bmoff;
+
+    P->htx.resize(ntx);
+    std::vector<int64_t> foff(ntx + 1, 0);
+    int lat = 0, max_nlat = 0;
+    for (int i = 0; i < ntx; ++i) {
+        P->htx[i].foff = foff[i];
+        P->htx[i].fn = sp.tx_n[i];
+        P->htx[i].lat0 = lat;
+        P->htx[i].nlat = sp.tx_L[i];
+        foff[i + 1] = foff[i] + sp.tx_n[i];
+        lat += sp.tx_L[i];
+        max_nlat = std::max(max_nlat, sp.tx_L[i]);
+    }
+
+    MR1L_HIP_TRY(P->desc.upload(P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
+    MR1L_HIP_TRY(P->tx.upload(P->htx.data(), P->htx.size() * sizeof(TxDesc)));
+    MR1L_HIP_TRY(P->tx_foff.upload(foff.data(), foff.size() * sizeof(int64_t)));
+    MR1L_HIP_TRY(P->z.upload(zred.data(), zred.size() * sizeof(int64_t)));
+    MR1L_HIP_TRY(P->small.upload(smalls.data(), smalls.size() * sizeof(int)));
+    MR1L_HIP_TRY(P->large.upload(larges.data(), larges.size() * sizeof(int)));
+    MR1L_HIP_TRY(P->t0c.upload(t0c.data(), t0c.size() * sizeof(int)));
+    MR1L_HIP_TRY(P->t0r.upload(t0r.data(), t0r.size() * sizeof(int)));
+    MR1L_HIP_TRY(P->bitmaps.alloc((size_t)std::max<int64_t>(1, P->bm_total) * sizeof(uint32_t)));
+    MR1L_HIP_TRY(P->filt.alloc((size_t)std::max<int64_t>(1, P->filt_total) * sizeof(cx<T>)));
+    MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->n_rhs) * sizeof(cx<T>)));
+
+    TxArgs& a = P->args;
+    a.desc = P->desc.as<LatDesc>();
+    a.L = L;
+    a.tx = P->tx.as<TxDesc>();
+    a.tx_foff = P->tx_foff.as<int64_t>();
+    a.ntx = ntx;
+    a.max_nlat = max_nlat;
+    a.z = P->z.as<int64_t>();
+    a.n = n;
+    a.n_rhs = P->n_rhs;
+    a.samp_stride = P->sum_M;
+    a.work_stride = P->work_stride;
+    a.bitmaps = P->bitmaps.as<uint32_t>();
+    a.bm_total = P->bm_total;
+    a.large = P->large.as<int>();
+    a.tile0_col = P->t0c.as<int>();
+    a.tile0_row = P->t0r.as<int>();
+    a.nlarge = (int)larges.size();
+    a.tiles_col = tc;
+    a.tiles_row = tr;
+    a.small = P->small.as<int>();
+    a.nsmall = (int)smalls.size();
+
+    if (!twiddles<T>(sp.device) || !twiddles<double>(sp.device)) {
+        set_error("could not allocate twiddle tables");
+        return MR1L_ERR_NOMEM;
+    }
+    build_filters<T>(P->hdesc.data(), L, a.desc, P->filt.as<cx<T>>(), P->filt_total, sp.device, nullptr);
+    MR1L_HIP_TRY(hipGetLastError());
+    MR1L_HIP_TRY(hipDeviceSynchronize());
+    *out = guard.release();
+    return MR1L_OK;
+}
+
+mr1l_status plan_create(const PlanSpec& sp, Plan** out) {
+    if (sp.d < 1 || sp.d > 64) {
+        set_error("d must be in 1..64");
+        return MR1L_ERR_ARG;
+    }
+    if (sp.n_rhs < 1) {
+        set_error("n_rhs must be >= 1");
+        return MR1L_ERR_ARG;
+    }
+    if (sp.tx_n.size() != sp.tx_L.size() || sp.tx_n.empty()) {
+        set_error("inconsistent transform description");
+        return MR1L_ERR_ARG;
+    }
+    return sp.dtype == MR1L_C128 ? plan_create_t<double>(sp, out) : plan_create_t<float>(sp, out);
+}
+
+// ---- stage timing ----------------------------------------------------------------------------------
+struct StageTimer {
+    Plan* p;
+    hipStream_t s;
+    int stage = -1;
+    hipEvent_t a = nullptr;
+    StageTimer(Plan* p_, hipStream_t s_) : p(p_), s(s_) {}
+    hipEvent_t get() {
+        if (!p->free_events.empty()) {
+            hipEvent_t e = p->free_events.back();
+            p->free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        hipEventCreate(&e);
+        return e;
+    }
+    void begin(int st) {
+        if (!p->timing) return;
+        stage = st;
+        a = get();
+        hipEventRecord(a, s);
+    }
+    void end() {
+        if (!p->timing || stage < 0) return;
+        hipEvent_t b = get();
+        hipEventRecord(b, s);
+        p->pending.push_back({stage, a, b});
+        stage = -1;
+    }
+};
+
+template <typename T>
+static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
+    const TxArgs& a = p->args;
+    const bool eval = p->weights == MR1L_W_EVAL;
+    cx<T>* work = p->work.as<cx<T>>();
+    const cx<T>* filt = p->filt.as<cx<T>>();
+    StageTimer tm(p, s);
+    if (!eval) {
+        tm.begin(0);
+        launch_clear_u32<T>(a.bitmaps, a.bm_total, s);
+        launch_residue_hist<T>(a, s);
+        tm.end();
+    }
+    if (a.nsmall) {
+        tm.begin(1);
+        launch_bluestein_small<T>(a, y, a.samp_stride, true, work, filt, work, a.work_stride, false, -1, !eval, s);
+        tm.end();
+    }
+    if (a.nlarge) {
+        tm.begin(2);
+        launch_p1<T>(a, y, a.samp_stride, true, work, -1, s);
+        tm.end();
+        tm.begin(3);
+        launch_p2<T>(a, work, filt, -1, s);
+        tm.end();
+        tm.begin(4);
+        launch_p3<T>(a, work, work, a.work_stride, false, -1, !eval, s);
+        tm.end();
+    }
+    tm.begin(5);
+    launch_gather<T>(a, work, c, eval, s);
+    tm.end();
+    MR1L_HIP_TRY(hipGetLastError());
+    return MR1L_OK;
+}
+
+template <typename T>
+static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
+    const TxArgs& a = p->args;
+    const bool eval = p->weights == MR1L_W_EVAL;
+    cx<T>* work = p->work.as<cx<T>>();
+    const cx<T>* filt = p->filt.as<cx<T>>();
+    StageTimer tm(p, s);
+    if (!eval) {
+        tm.begin(0);
+        launch_clear_u32<T>(a.bitmaps, a.bm_total, s);
+        launch_residue_hist<T>(a, s);
+        tm.end();
+    }
+    tm.begin(6);
+    launch_clear_bins<T>(a, work, s);
+    launch_scatter<T>(a, c, work, eval, s);
+    tm.end();
+    if (a.nsmall) {
+        tm.begin(1);
+        launch_bluestein_small<T>(a, work, a.work_stride, false, work, filt, y, a.samp_stride, true, +1, !eval, s);
+        tm.end();
+    }
+    if (a.nlarge) {
+        tm.begin(2);
+        launch_p1<T>(a, work, a.work_stride, false, work, +1, s);
+        tm.end();
+        tm.begin(3);
+        launch_p2<T>(a, work, filt, +1, s);
+        tm.end();
+        tm.begin(4);
+        launch_p3<T>(a, work, y, a.samp_stride, true, +1, !eval, s);
+        tm.end();
+    }
+    MR1L_HIP_TRY(hipGetLastError());
+    return MR1L_OK;
+}
+
+mr1l_status plan_forward(Plan* p, const void* samples, void* coeffs, hipStream_t s) {
+    if (p->dtype == MR1L_C128) return forward_t<double>(p, (const cx<double>*)samples, (cx<double>*)coeffs, s);
+    return forward_t<float>(p, (const cx<float>*)samples, (cx<float>*)coeffs, s);
+}
+
+mr1l_status plan_adjoint(Plan* p, const void* coeffs, void* samples, hipStream_t s) {
+    if (p->dtype == MR1L_C128) return adjoint_t<double>(p, (const cx<double>*)coeffs, (cx<double>*)samples, s);
+    return adjoint_t<float>(p, (const cx<float>*)coeffs, (cx<float>*)samples, s);
+}
+
+mr1l_status plan_alias(Plan* p, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s) {
+    launch_clear_u32<float>(p->args.bitmaps, p->args.bm_total, s);
+    launch_residue_hist<float>(p->args, s);
+    launch_alias_export(p->args, res, uniq, counter, s);
+    MR1L_HIP_TRY(hipGetLastError());
+    return MR1L_OK;
+}
+
+}  // namespace mr1l
+
+using namespace mr1l;
+
+#define MR1L_GUARD_BEGIN try {
+#define MR1L_GUARD_END                                  \
+    }                                                   \
+    catch (const std::bad_alloc&) {                     \
+        set_error("host allocation failed");            \
+        return MR1L_ERR_NOMEM;                          \
+    }                                                   \
+    catch (const std::exception& ex) {                  \
+        set_error(ex.what());                           \
+        return MR1L_ERR_ARG;                            \
+    }
+
+extern "C" {
+
+const char* mr1l_last_error(void) { return g_err.c_str(); }
+const char* mr1l_version(void) { return "mr1l 0.1 (gfx950)"; }
+
+mr1l_status mr1l_plan(int d, int64_t n, const int32_t* freqs, int L, const int64_t* M, const int64_t* z,
+                      mr1l_dtype dtype, mr1l_weights weights, int64_t n_rhs, int device, mr1l_plan_t* out) {
+    MR1L_GUARD_BEGIN
+    clear_error();
+    if (!out || n < 0 || L < 0 || (n > 0 && !freqs) || (L > 0 && (!M || !z)) ||
+        (dtype != MR1L_C64 && dtype != MR1L_C128) || (weights != MR1L_W_PAPER && weights != MR1L_W_EVAL)) {
+        set_error("invalid argument to mr1l_plan");
+        return MR1L_ERR_ARG;
+    }
+    PlanSpec sp;
+    sp.d = d;
+    sp.dtype = dtype;
+    sp.weights = weights;
+    sp.n_rhs = n_rhs;
+    sp.device = device;
+    sp.host_freqs = freqs;
+    sp.tx_n = {n};
+    sp.tx_L = {L};
+    sp.M.assign(M, M + L);
+    sp.z.assign(z, z + (size_t)L * (d > 0 ? d : 0));
+    Plan* p = nullptr;
+    mr1l_status st = plan_create(sp, &p);
+    if (st == MR1L_OK) *out = (mr1l_plan_t)p;
+    return st;
+    MR1L_GUARD_END
+}
+
+mr1l_status mr1l_forward(mr1l_plan_t plan, const void* samples, void* coeffs, void* stream) {
+    MR1L_GUARD_BEGIN
+    clear_error();
+    Plan* p = (Plan*)plan;
+    if (!p || (p->sum_M > 0 && !samples) || (p->n > 0 && !coeffs)) {
+        set_error("invalid argument to mr1l_forward");
+        return MR1L_ERR_ARG;
+    }
+    MR1L_HIP_TRY(hipSetDevice(p->device));
+    return plan_forward(p, samples, coeffs, (hipStream_t)stream);
+    MR1L_GUARD_END
+}
+
+mr1l_status mr1l_adjoint(mr1l_plan_t plan, const void* coeffs, void* samples, void* stream) {
+    MR1L_GUARD_BEGIN
+    clear_error();
+    Plan* p = (Plan*)plan;
+    if (!p || (p->sum_M > 0 && !samples) || (p->n > 0 && !coeffs)) {
+        set_error("invalid argument to mr1l_adjoint");
+        return MR1L_ERR_ARG;
+    }
+    MR1L_HIP_TRY(hipSetDevice(p->device));
+    return plan_adjoint(p, coeffs, samples, (hipStream_t)stream);
+    MR1L_GUARD_END
+}
+
+mr1l_status mr1l_alias(mr1l_plan_t plan, int64_t* residues, uint8_t* unaliased, uint8_t* counter, void* stream) {
+    MR1L_GUARD_BEGIN
+    clear_error();
+    Plan* p = (Plan*)plan;
+    if (!p) {
+        set_error("null plan");
+        return MR1L_ERR_ARG;
+    }
+    MR1L_HIP_TRY(hipSetDevice(p->device));
+    return plan_alias(p, residues, unaliased, counter, (hipStream_t)stream);
+    MR1L_GUARD_END
+}
+
+mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_uncovered, int64_t* fft_lengths) {
+    MR1L_GUARD_BEGIN
+    clear_error();
+    Plan* p = (Plan*)plan;
+    if (!p) {
+        set_error("null plan");
+        return MR1L_ERR_ARG;
+    }
+    if (sample_offsets) std::copy(p->samp_off.begin(), p->samp_off.end(), sample_offsets);
+    if (fft_lengths)
+        for (int l = 0; l < p->L; ++l) fft_lengths[l] = (int64_t)1 << p->hdesc[l].lgN;
+    if (n_uncovered) {
+        MR1L_HIP_TRY(hipSetDevice(p->device));
+        DevMem cnt;
+        MR1L_HIP_TRY(cnt.alloc((size_t)std::max<int64_t>(1, p->n)));
+        mr1l_status st = plan_alias(p, nullptr, nullptr, cnt.as<uint8_t>(), nullptr);
+        if (st != MR1L_OK) return st;
+        std::vector<uint8_t> h((size_t)p->n);
+        if (p->n) MR1L_HIP_TRY(hipMemcpy(h.data(), cnt.p, (size_t)p->n, hipMemcpyDeviceToHost));
+        int64_t u = 0;
+        for (uint8_t v : h) u += (v == 0);
+        *n_uncovered = u;
+    }
+    return MR1L_OK;
+    MR1L_GUARD_END
+}
+
+mr1l_status mr1l_destroy(mr1l_plan_t plan) {
+    if (!plan) return MR1L_OK;
+    Plan* p = (Plan*)plan;
+    hipSetDevice(p->device);
+    delete p;
+    return MR1L_OK;
+}
+
+mr1l_status mr1l_timing_enable(mr1l_plan_t plan, int enable) {
+    Plan* p = (Plan*)plan;
+    if (!p) return MR1L_ERR_ARG;
+    p->timing = enable != 0;
+    return MR1L_OK;
+}
+
+mr1l_status mr1l_timing_read(mr1l_plan_t plan, double* ms_sum, int64_t* launches, const char** names) {
+    MR1L_GUARD_BEGIN
+    Plan* p = (Plan*)plan;
+    if (!p) return MR1L_ERR_ARG;
+    MR1L_HIP_TRY(hipSetDevice(p->device));
+    for (auto& r : p->pending) {
+        MR1L_HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        MR1L_HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        p->ms_sum[r.stage] += ms;
+        p->launches[r.stage] += 1;
+        p->free_events.push_back(r.a);
+        p->free_events.push_back(r.b);
+    }
+    p->pending.clear();
+    for (int i = 0; i < MR1L_NSTAGES; ++i) {
+        if (ms_sum) ms_sum[i] = p->ms_sum[i];
+        if (launches) launches[i] = p->launches[i];
+        if (names) names[i] = kStageNames[i];
+        p->ms_sum[i] = 0;
+        p->launches[i] = 0;
+    }
+    return MR1L_OK;
+    MR1L_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Host runtime of libmr1l: device buffers, error reporting, plans, random streams.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "mr1l.h"
+
+namespace mr1l {
+
+// thread-local error text behind mr1l_last_error()
+void set_error(const std::string& msg);
+void clear_error();
+
+#define MR1L_HIP_TRY(expr)                                                                           \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            ::mr1l::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+            return e_ == hipErrorOutOfMemory ? MR1L_ERR_NOMEM : MR1L_ERR_HIP;                        \
+        }                                                                                            \
+    } while (0)
+
+// Owning device allocation.
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b) {
+        release();
+        bytes = b;
+        if (b == 0) return hipSuccess;
+        return hipMalloc(&p, b);
+    }
+    hipError_t upload(const void* h, size_t b) {
+        hipError_t e = alloc(b);
+        if (e != hipSuccess || b == 0) return e;
+        return hipMemcpy(p, h, b, hipMemcpyHostToDevice);
+    }
+    template <typename U> U* as() const { return (U*)p; }
+};
+
+// Counter-based SplitMix64 streams (published generator; the key derivation is this project's):
+//   key(seed, f1..fm): k = seed; k = mix64(k + GAMMA (f + 1)) for each field f
+//   draw(k, c) = mix64(k + GAMMA (c + 1))
+struct Rng {
+    static constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
+    static uint64_t mix64(uint64_t x) {
+        x ^= x >> 30;
+        x *= 0xBF58476D1CE4E5B9ull;
+        x ^= x >> 27;
+        x *= 0x94D049BB133111EBull;
+        x ^= x >> 31;
+        return x;
+    }
+    static uint64_t key(uint64_t seed, std::initializer_list<int64_t> fields) {
+        uint64_t k = seed;
+        for (int64_t f : fields) k = mix64(k + GAMMA * (uint64_t)(f + 1));
+        return k;
+    }
+    static uint64_t draw(uint64_t k, uint64_t c) { return mix64(k + GAMMA * (c + 1)); }
+    static double uniform01(uint64_t k, uint64_t c) { return (double)(draw(k, c) >> 11) * 0x1.0p-53; }
+    // unbiased integer in [0, M): rejection of draws below 2^64 mod M; advances *c
+    static uint64_t uniform_int(uint64_t k, uint64_t* c, uint64_t M) {
+        const uint64_t floor_reject = (0 - M) % M;   // == 2^64 mod M
+        for (;;) {
+            const uint64_t u = draw(k, (*c)++);
+            if (u >= floor_reject) return u % M;
+        }
+    }
+    enum Purpose : int64_t { Z = 1, ANCHOR1D = 2, ANCHOR = 3, NOISE = 4 };
+};
+
+// Description of the transforms a plan holds.  A plain plan has one transform; a batched plan
+// stacks several independent ones (own frequencies, own lattices).
+struct PlanSpec {
+    int d = 0;
+    mr1l_dtype dtype = MR1L_C64;
+    mr1l_weights weights = MR1L_W_PAPER;
+    int64_t n_rhs = 1;
+    int device = 0;
+    // frequencies: either host int32 [n][d] or device component-major packed data
+    const int32_t* host_freqs = nullptr;
+    const void* dev_freqs = nullptr;   // component-major [d][n] of type ktype (not owned)
+    int dev_ktype = K_I32;
+    int64_t dev_maxabs = 0;            // max |k| of the device frequencies
+    bool check_distinct = true;
+    // transforms
+    std::vector<int64_t> tx_n;         // frequencies per transform
+    std::vector<int32_t> tx_L;         // lattices per transform
+    std::vector<int64_t> M;            // all lattice sizes, transform after transform
+    std::vector<int64_t> z;            // [sum L][d]
+};
+
+struct Plan {
+    int device = 0;
+    int d = 0;
+    int64_t n = 0;
+    int L = 0;
+    mr1l_dtype dtype = MR1L_C64;
+    mr1l_weights weights = MR1L_W_PAPER;
+    int64_t n_rhs = 1;
+    std::vector<LatDesc> hdesc;
+    std::vector<TxDesc> htx;
+    std::vector<int64_t> samp_off;     // [L + 1]
+    int64_t sum_M = 0;
+    int64_t work_stride = 0;
+    int64_t filt_total = 0;
+    int64_t bm_total = 0;
+    DevMem freqs, desc, tx, tx_foff, z, bitmaps, filt, work, large, small, t0c, t0r;
+    TxArgs args{};
+    // per-stage timing
+    bool timing = false;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> free_events;
+    double ms_sum[MR1L_NSTAGES] = {0};
+    int64_t launches[MR1L_NSTAGES] = {0};
+    ~Plan();
+};
+
+mr1l_status plan_create(const PlanSpec& spec, Plan** out);
+mr1l_status plan_forward(Plan* p, const void* samples, void* coeffs, hipStream_t s);
+mr1l_status plan_adjoint(Plan* p, const void* coeffs, void* samples, hipStream_t s);
+mr1l_status plan_alias(Plan* p, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s);
+
+// Alg. 1 (+ repetition, Alg. 3 step 2b) on device-resident or host frequencies.
+struct ConstructResult {
+    std::vector<int64_t> M, z;
+    int calls = 0;
+    int64_t uncovered = 0;
+};
+mr1l_status construct_lattices(int d, int64_t n, const int32_t* host_freqs, const void* dev_freqs, int ktype,
+                               int64_t maxabs, int64_t expansion, double c, double gamma, int b, uint64_t seed,
+                               int64_t t, int device, hipStream_t s, ConstructResult* out);
+
+}  // namespace mr1l
