@@ -1,0 +1,186 @@
+"""Benchmark: multiple rank-1 lattice FFT, forward + adjoint, on one MI355X.
+
+Workload (one "step"): the standalone transform pair on |I| = 2^16 frequencies drawn uniformly
+from [-64,64]^10, L = 16 lattices with prime sizes uniform in [2^16, 2^17], complex64 samples
+(CN(0,1)) already resident in HBM.  A step runs every stage of the hot path twice (forward:
+residues, alias histograms, prime-length DFTs, gather; adjoint: residues, alias histograms,
+scatter, prime-length DFTs).  value = |I| / (time of forward + adjoint) in frequencies per second.
+
+Prints ONE JSON line (rank 0).  Extra fields: per-stage device times (HIP events on the launch
+stream), the roofline of the dominant kernel, and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_TFLOPS = 157.3     # MI355X published FP32 vector peak
+FP64_VECTOR_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def fft_flops(N: int) -> float:
+    """Nominal cost of a complex FFT of length N (5 N log2 N)."""
+    return 5.0 * N * math.log2(N) if N > 1 else 0.0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 (multi-GPU sharding "
+                                   "is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1711_05152_amd.mr1l import Plan
+    from workloads import standalone_c2
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    p = standalone_c2()
+    n, d, L = p.n, p.d, len(p.M)
+    sumM = int(p.M.sum())
+    plan = Plan(p.freqs, p.M, p.z, dtype="c64", weights="paper", n_rhs=1, device=0)
+    y = torch.from_numpy(p.samples).to(dev, torch.complex64)
+    c_in = torch.from_numpy(p.coeffs).to(dev, torch.complex64)
+    c_out = plan.empty_coeffs()
+    y_out = plan.empty_samples()
+
+    def step():
+        plan.forward(y, out=c_out)
+        plan.adjoint(c_in, out=y_out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_wall = (t1 - t0) * 1e3 / args.steps
+    ms_event = ev0.elapsed_time(ev1) / args.steps
+
+    # per-stage device time: HIP events recorded by the library on the launch stream
+    plan.timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    stages = plan.timing_read()
+    plan.timing(False)
+    per_launch = {k: v[0] / v[1] for k, v in stages.items()}
+    per_step = {k: v[0] / args.steps for k, v in stages.items()}
+
+    # ---- roofline of the dominant kernel ------------------------------------------------------------
+    Ns = [int(v) for v in plan.fft_lengths]
+    dom = max(per_step, key=per_step.get)
+    lg = [int(round(math.log2(N))) for N in Ns]
+    if dom == "bluestein_p2":
+        # row FFTs (forward + inverse) of length N2 on N1 rows, per lattice, nominal 5 N log2 N each
+        flops = sum(2 * fft_flops(1 << (g - g // 2)) * (1 << (g // 2)) for g in lg)
+    elif dom in ("bluestein_p1", "bluestein_p3"):
+        flops = sum(fft_flops(1 << (g // 2)) * (1 << (g - g // 2)) for g in lg)
+    elif dom == "bluestein_small":
+        flops = sum(2 * fft_flops(N) for N in Ns)
+    else:
+        flops = None
+    dom_ms = per_launch[dom]
+    if flops is not None:
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_TFLOPS, "traffic": None,
+                "avg_launch_ms": dom_ms, "work_per_launch": flops}
+    else:
+        nbytes = 8 * sumM + n * d + 8 * n
+        achieved = nbytes / (dom_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": dom_ms,
+                "work_per_launch": nbytes}
+
+    # end-to-end algorithmic bytes (samples + packed frequencies + coefficients, both directions)
+    alg_bytes = 2 * (8 * sumM + n * d * 1 + 8 * n)
+    e2e = {"alg_bytes_per_step": alg_bytes, "GBs": alg_bytes / (ms_event * 1e-3) / 1e9,
+           "frac_hbm": alg_bytes / (ms_event * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    # ---- CPU oracle baseline ------------------------------------------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import mr1l as O
+        threads = 1
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        iters = 0
+        tc0 = time.perf_counter()
+        while True:
+            O.forward(p.freqs, p.M, p.z, p.samples)
+            O.adjoint(p.freqs, p.M, p.z, p.coeffs)
+            iters += 1
+            if time.perf_counter() - tc0 > args.cpu_seconds:
+                break
+        tcpu = (time.perf_counter() - tc0) / iters
+        cpu = {"value": n / tcpu, "unit": "freqs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{iters} forward+adjoint pairs of the same |I|=2^16 workload (numpy FFT tier, "
+                         f"FP64), {tcpu:.3f} s each"}
+
+    line = {
+        "metric": "mr1l-FFT freqs/s fwd+adj (|I|=2^16,d=10)",
+        "value": n / (ms_event * 1e-3),
+        "unit": "freqs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_event,
+        "ms_per_step_wall": ms_wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "standalone mr1l-FFT forward+adjoint: |I|=2^16 uniform in [-64,64]^10, "
+                               "L=16 prime M_l uniform in [2^16,2^17], complex64 samples CN(0,1)",
+                   "n": n, "d": d, "L": L, "sum_M": sumM, "fft_lengths": sorted(set(Ns)),
+                   "residues": "int64"},
+        "roofline": roof,
+        "end_to_end": e2e,
+        "stages_ms_per_step": per_step,
+        "stages_ms_per_launch": per_launch,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

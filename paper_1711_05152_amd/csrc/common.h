@@ -57,6 +57,16 @@ struct TxDesc {
     int32_t nlat;
 };
 
+// One workgroup of the alias-histogram pass: lattice l, bins [m0, m1) (multiples of 32 except
+// possibly m1 = M), of transform tx.
+struct HistTile {
+    int32_t l;
+    int32_t tx;
+    int32_t m0;
+    int32_t m1;
+};
+constexpr int kHistMaxBins = 1 << 18;   // 2 x 2^18 bits = 64 KiB of LDS bitmaps per workgroup
+
 // Frequencies are kept component-major (structure of arrays) in the narrowest signed integer
 // type that holds them.
 enum KType { K_I8 = 0, K_I16 = 1, K_I32 = 2 };
@@ -67,7 +77,7 @@ constexpr int kTwLg = 12;          // twiddle table e^{-2 pi i m / 4096}, m < 40
 
 // Elements held in LDS by one four-step tile (fp32: 64 KiB, fp64: 64 KiB).
 template <typename T> struct TileElems;
-template <> struct TileElems<float> { static constexpr int lg = 13; };
+template <> struct TileElems<float> { static constexpr int lg = 12; };
 template <> struct TileElems<double> { static constexpr int lg = 12; };
 
 // ---- launchers (defined in the .hip files) ---------------------------------------------------------
@@ -94,6 +104,9 @@ struct TxArgs {
     int64_t work_stride;      // elements per rhs in the work area
     uint32_t* bitmaps;        // device alias bitmaps
     int64_t bm_total;         // words of all bitmaps
+    int32_t* res32;           // device residues [max_nlat][n] (slot = lattice index within its transform)
+    const HistTile* hist;     // device [nhist]
+    int nhist;
     // four-step tiling (large lattices)
     const int* large;         // device [nlarge] lattice indices
     const int* tile0_col;     // device [nlarge + 1] column-tile prefix sums
@@ -106,10 +119,10 @@ struct TxArgs {
 
 template <typename T> const cx<T>* twiddles(int device);   // e^{-2 pi i m/4096}, m < 4096
 
-template <typename T>
 void launch_clear_u32(uint32_t* p, int64_t words, hipStream_t s);
-template <typename T>
-void launch_residue_hist(const TxArgs& a, hipStream_t s);
+// residues of every (lattice, frequency) into res32, then (if histogram) the per-lattice 2-bit
+// alias histograms (LDS atomics, one workgroup per HistTile) written to the global bitmaps
+void launch_alias(const TxArgs& a, bool histogram, hipStream_t s);
 template <typename T>
 void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval, hipStream_t s);
 template <typename T>

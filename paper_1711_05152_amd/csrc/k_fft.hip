@@ -64,21 +64,50 @@ const cx<T>* twiddles(int device) {
 template const cx<float>* twiddles<float>(int);
 template const cx<double>* twiddles<double>(int);
 
-// e^{-2 pi i e / 2^lgN} for 0 <= e < 2^lgN <= 2^24 from the two-level table.
+// e^{i pi x}
+template <typename T> __device__ __forceinline__ cx<T> cispi(double x);
+template <> __device__ __forceinline__ cx<float> cispi<float>(double x) {
+    float s, c;
+    sincospif((float)x, &s, &c);
+    return {c, s};
+}
+template <> __device__ __forceinline__ cx<double> cispi<double>(double x) {
+    double s, c;
+    sincospi(x, &s, &c);
+    return {c, s};
+}
+
+// e^{-2 pi i e / 2^lgN} for 0 <= e < 2^lgN <= 2^24; the argument -2e/2^lgN is exact in T.
 template <typename T>
-__device__ __forceinline__ cx<T> tw_big(const cx<T>* __restrict__ tw, uint32_t e, int lgN) {
-    const uint32_t e24 = e << (24 - lgN);
-    return cmul(tw[e24 >> 12], tw[4096 + (e24 & 4095u)]);
+__device__ __forceinline__ cx<T> tw_pow2(uint32_t e, int lgN) {
+    T s, c;
+    const T x = -(T)e * (T)ldexp(1.0, 1 - lgN);
+    if constexpr (sizeof(T) == 4) sincospif(x, &s, &c);
+    else sincospi(x, &s, &c);
+    return {c, s};
+}
+
+// (n^2 mod 2M) as an integer-valued double: every intermediate is an integer below 2^53 for
+// n < 2^23, so the remainder is exact after at most one correction of the quotient estimate.
+__device__ __forceinline__ double sq_mod_2M(int64_t n, int64_t M, double inv2M) {
+    const double nn = (double)n * (double)n;
+    const double m2 = 2.0 * (double)M;
+    double q = nn - m2 * floor(nn * inv2M);
+    if (q < 0.0) q += m2;
+    else if (q >= m2) q -= m2;
+    return q;
 }
 
 // e^{sign i pi (n^2 mod 2M)/M}
 template <typename T>
 __device__ __forceinline__ cx<T> chirp(int64_t n, int64_t M, double invM, int sign) {
-    const uint64_t q = ((uint64_t)n * (uint64_t)n) % (uint64_t)(2 * M);
-    double s, c;
-    sincospi((double)sign * ((double)q * invM), &s, &c);
-    return make_cx<T>((T)c, (T)s);
+    return cispi<T>((double)sign * (sq_mod_2M(n, M, 0.5 * invM) * invM));
 }
+
+// LDS index with one pad slot after every 8 elements: strided Stockham writes and column loads
+// then spread over the banks instead of piling onto a few.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+template <int ELEMS> struct Padded { static constexpr int v = ELEMS + (ELEMS >> 3) + 64; };
 
 // ---- in-register DFTs ------------------------------------------------------------------------------
 template <typename T, int SIGN>
@@ -147,9 +176,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int lgN, int nseq, int S, 
         const int g = threadIdx.x + u * kThreads;
         if (g < total) {
             const int b = g >> lgNb, j = g & (nbf - 1);
-            const cx<T>* src = buf + b * S + j;
+            const int base = b * S + j;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = src[r << lgNb];
+            for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(base + (r << lgNb))];
         }
     }
     __syncthreads();
@@ -161,16 +190,26 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int lgN, int nseq, int S, 
             const int k = j & ((1 << lgNs) - 1);
             if (lgNs > 0) {
                 const int step = k << (kTwLg - lgNs - LR);   // w_{Ns R}^{k} = tw[k 4096/(Ns R)]
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    const cx<T> w = tw[r * step];
-                    v[u][r] = SIGN < 0 ? cmul(v[u][r], w) : cmulc(v[u][r], w);
+                // powers w^r from table values w, w^2, w^4 (exact entries) and at most two products
+                cx<T> w[R];
+                w[1] = tw[step];
+                if (R >= 4) {
+                    w[2] = tw[2 * step];
+                    w[3] = cmul(w[1], w[2]);
                 }
+                if (R >= 8) {
+                    w[4] = tw[4 * step];
+                    w[5] = cmul(w[1], w[4]);
+                    w[6] = cmul(w[2], w[4]);
+                    w[7] = cmul(w[3], w[4]);
+                }
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[u][r] = SIGN < 0 ? cmul(v[u][r], w[r]) : cmulc(v[u][r], w[r]);
             }
             Dft<T, R, SIGN>::run(v[u]);
-            cx<T>* dst = buf + b * S + ((j - k) << LR) + k;
+            const int base = b * S + ((j - k) << LR) + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r << lgNs] = v[u][r];
+            for (int r = 0; r < R; ++r) buf[pidx(base + (r << lgNs))] = v[u][r];
         }
     }
     __syncthreads();
@@ -211,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const cx<T>* __restri
                                                  cx<T>* work, int sign, const cx<T>* __restrict__ tw) {
     constexpr int LGE = TileElems<T>::lg;
     constexpr int E = (1 << LGE) / kThreads;
-    __shared__ cx<T> lds[(1 << LGE) + 256];
+    __shared__ cx<T> lds[Padded<(1 << LGE) + 256>::v];
     const int i = find_seg(a.tile0_col, a.nlarge + 1, blockIdx.x);
     const LatDesc D = a.desc[a.large[i]];
     const int lgN1 = D.lgN1, lgN2 = D.lgN2;
@@ -232,15 +271,21 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const cx<T>* __restri
             v = in[n];
             if (SRC != 2) v = cmul(v, chirp<T>(n, D.M, D.invM, sign));
         }
-        lds[col * S + n1] = v;
+        lds[pidx(col * S + n1)] = v;
     }
     __syncthreads();
     lds_fft<T, E, -1>(lds, lgN1, C, S, tw);
-    for (int e = threadIdx.x; e < total; e += kThreads) {
-        const int col = e & (C - 1), k1 = e >> lgC;
-        const int n2 = c0 + col;
-        const cx<T> v = cmul(lds[col * S + k1], tw_big(tw, (uint32_t)(n2 * k1), D.lgN));
-        w[((int64_t)k1 << lgN2) + n2] = v;
+    {
+        // this thread's column n2 is fixed and k1 advances by kThreads/C: w_N^{n2 k1} by recurrence
+        const int col = threadIdx.x & (C - 1), n2 = c0 + col;
+        const int dk = kThreads >> lgC;
+        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * (threadIdx.x >> lgC)), D.lgN);
+        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 * dk) & ((1 << D.lgN) - 1)), D.lgN);
+        for (int e = threadIdx.x; e < total; e += kThreads) {
+            const int k1 = e >> lgC;
+            w[((int64_t)k1 << lgN2) + n2] = cmul(lds[pidx(col * S + k1)], wk);
+            wk = cmul(wk, ws);
+        }
     }
 }
 
@@ -251,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, cx<T>* work, const cx
                                                  const cx<T>* __restrict__ tw) {
     constexpr int LGE = TileElems<T>::lg;
     constexpr int E = (1 << LGE) / kThreads;
-    __shared__ cx<T> lds[1 << LGE];
+    __shared__ cx<T> lds[Padded<(1 << LGE)>::v];
     const int i = find_seg(a.tile0_row, a.nlarge + 1, blockIdx.x);
     const LatDesc D = a.desc[a.large[i]];
     const int lgN1 = D.lgN1, lgN2 = D.lgN2;
@@ -260,17 +305,17 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, cx<T>* work, const cx
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off + ((int64_t)r0 << lgN2);
     const int total = 1 << (lgR + lgN2);
-    for (int e = threadIdx.x; e < total; e += kThreads) lds[e] = w[e];
+    for (int e = threadIdx.x; e < total; e += kThreads) lds[pidx(e)] = w[e];
     __syncthreads();
     lds_fft<T, E, -1>(lds, lgN2, 1 << lgR, 1 << lgN2, tw);
     if (CONV) {
         const cx<T>* f = filt + D.filt_off + ((int64_t)r0 << lgN2);
         for (int e = threadIdx.x; e < total; e += kThreads)
-            lds[e] = sign < 0 ? cmul(lds[e], f[e]) : cmulc(lds[e], f[e]);
+            lds[pidx(e)] = sign < 0 ? cmul(lds[pidx(e)], f[e]) : cmulc(lds[pidx(e)], f[e]);
         __syncthreads();
         lds_fft<T, E, +1>(lds, lgN2, 1 << lgR, 1 << lgN2, tw);
     }
-    for (int e = threadIdx.x; e < total; e += kThreads) w[e] = lds[e];
+    for (int e = threadIdx.x; e < total; e += kThreads) w[e] = lds[pidx(e)];
 }
 
 // ---- four-step stage 3 -----------------------------------------------------------------------------
@@ -279,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, cx<T>* work, cx<T>* d
                                                  int scale_by_invM, const cx<T>* __restrict__ tw) {
     constexpr int LGE = TileElems<T>::lg;
     constexpr int E = (1 << LGE) / kThreads;
-    __shared__ cx<T> lds[(1 << LGE) + 256];
+    __shared__ cx<T> lds[Padded<(1 << LGE) + 256>::v];
     const int i = find_seg(a.tile0_col, a.nlarge + 1, blockIdx.x);
     const LatDesc D = a.desc[a.large[i]];
     const int lgN1 = D.lgN1, lgN2 = D.lgN2;
@@ -290,10 +335,16 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, cx<T>* work, cx<T>* d
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
     const int total = N1 << lgC;
-    for (int e = threadIdx.x; e < total; e += kThreads) {
-        const int col = e & (C - 1), k1 = e >> lgC;
-        const int n2 = c0 + col;
-        lds[col * S + k1] = cmulc(w[((int64_t)k1 << lgN2) + n2], tw_big(tw, (uint32_t)(n2 * k1), D.lgN));
+    {
+        const int col = threadIdx.x & (C - 1), n2 = c0 + col;
+        const int dk = kThreads >> lgC;
+        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * (threadIdx.x >> lgC)), D.lgN);
+        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 * dk) & ((1 << D.lgN) - 1)), D.lgN);
+        for (int e = threadIdx.x; e < total; e += kThreads) {
+            const int k1 = e >> lgC;
+            lds[pidx(col * S + k1)] = cmulc(w[((int64_t)k1 << lgN2) + n2], wk);
+            wk = cmul(wk, ws);
+        }
     }
     __syncthreads();
     lds_fft<T, E, +1>(lds, lgN1, C, S, tw);
@@ -302,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, cx<T>* work, cx<T>* d
     for (int e = threadIdx.x; e < total; e += kThreads) {
         const int col = e & (C - 1), n1 = e >> lgC;
         const int64_t n = ((int64_t)n1 << lgN2) + c0 + col;
-        if (n < D.M) out[n] = cscale(cmul(lds[col * S + n1], chirp<T>(n, D.M, D.invM, sign)), sc);
+        if (n < D.M) out[n] = cscale(cmul(lds[pidx(col * S + n1)], chirp<T>(n, D.M, D.invM, sign)), sc);
     }
 }
 
@@ -313,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const cx<T>* __res
                                                     int64_t dst_stride, int sign, int scale_by_invM,
                                                     const cx<T>* __restrict__ tw) {
     constexpr int E = (1 << kSmallMaxLg) / kThreads;
-    __shared__ cx<T> lds[1 << kSmallMaxLg];
+    __shared__ cx<T> lds[Padded<(1 << kSmallMaxLg)>::v];
     const LatDesc D = a.desc[a.small[blockIdx.x]];
     const int64_t rhs = blockIdx.y;
     const int N = 1 << D.lgN;
@@ -321,32 +372,32 @@ __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const cx<T>* __res
     for (int n = threadIdx.x; n < N; n += kThreads) {
         cx<T> v = {(T)0, (T)0};
         if (n < D.M) v = cmul(in[n], chirp<T>(n, D.M, D.invM, sign));
-        lds[n] = v;
+        lds[pidx(n)] = v;
     }
     __syncthreads();
     lds_fft<T, E, -1>(lds, D.lgN, 1, N, tw);
     const cx<T>* f = filt + D.filt_off;
-    for (int n = threadIdx.x; n < N; n += kThreads) lds[n] = sign < 0 ? cmul(lds[n], f[n]) : cmulc(lds[n], f[n]);
+    for (int n = threadIdx.x; n < N; n += kThreads) lds[pidx(n)] = sign < 0 ? cmul(lds[pidx(n)], f[n]) : cmulc(lds[pidx(n)], f[n]);
     __syncthreads();
     lds_fft<T, E, +1>(lds, D.lgN, 1, N, tw);
     cx<T>* out = TO_SAMPLES ? dst + rhs * dst_stride + D.samp_off : work + rhs * a.work_stride + D.work_off;
     const T sc = scale_by_invM ? (T)D.invM : (T)1;
     for (int n = threadIdx.x; n < D.M; n += kThreads)
-        out[n] = cscale(cmul(lds[n], chirp<T>(n, D.M, D.invM, sign)), sc);
+        out[n] = cscale(cmul(lds[pidx(n)], chirp<T>(n, D.M, D.invM, sign)), sc);
 }
 
 // plain in-place forward DFT of the whole region (filter construction, one-block lattices)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_small_dft(TxArgs a, cx<T>* work, const cx<T>* __restrict__ tw) {
     constexpr int E = (1 << kSmallMaxLg) / kThreads;
-    __shared__ cx<T> lds[1 << kSmallMaxLg];
+    __shared__ cx<T> lds[Padded<(1 << kSmallMaxLg)>::v];
     const LatDesc D = a.desc[a.small[blockIdx.x]];
     const int N = 1 << D.lgN;
     cx<T>* w = work + D.work_off;
-    for (int n = threadIdx.x; n < N; n += kThreads) lds[n] = w[n];
+    for (int n = threadIdx.x; n < N; n += kThreads) lds[pidx(n)] = w[n];
     __syncthreads();
     lds_fft<T, E, -1>(lds, D.lgN, 1, N, tw);
-    for (int n = threadIdx.x; n < N; n += kThreads) w[n] = lds[n];
+    for (int n = threadIdx.x; n < N; n += kThreads) w[n] = lds[pidx(n)];
 }
 
 // b_l[n] = e^{+i pi n^2/M} for 0 <= n < M and at N - n for 0 < n < M, zero elsewhere (double)
@@ -360,10 +411,7 @@ __global__ void k_filter_fill(const LatDesc* __restrict__ desc, int L, cx<double
         else if (N - n < D.M) m = N - n;
         cx<double> v = {0.0, 0.0};
         if (m >= 0) {
-            const uint64_t q = ((uint64_t)m * (uint64_t)m) % (uint64_t)(2 * D.M);
-            double s, c;
-            sincospi((double)q * D.invM, &s, &c);
-            v = {c, s};
+            v = cispi<double>(sq_mod_2M(m, D.M, 0.5 * D.invM) * D.invM);
         }
         tmp[D.work_off + n] = v;
     }

@@ -197,6 +197,24 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     MR1L_HIP_TRY(P->large.upload(larges.data(), larges.size() * sizeof(int)));
     MR1L_HIP_TRY(P->t0c.upload(t0c.data(), t0c.size() * sizeof(int)));
     MR1L_HIP_TRY(P->t0r.upload(t0r.data(), t0r.size() * sizeof(int)));
+    // alias-histogram tiles: every lattice's bins split into ranges of <= 2^18 bins (multiples of
+    // 32), several per lattice when there are few lattices so that enough workgroups run
+    std::vector<HistTile> tiles;
+    {
+        const int rpl = std::max(1, std::min(8, 256 / std::max(1, L)));
+        int txi = 0;
+        for (int l = 0; l < L; ++l) {
+            while (txi + 1 < ntx && l >= P->htx[txi].lat0 + P->htx[txi].nlat) ++txi;
+            const int64_t M = P->hdesc[l].M;
+            int64_t nr = std::max<int64_t>((M + kHistMaxBins - 1) / kHistMaxBins, rpl);
+            nr = std::min<int64_t>(nr, (M + 31) / 32);
+            int64_t step = ((M + nr - 1) / nr + 31) / 32 * 32;
+            for (int64_t m0 = 0; m0 < M; m0 += step)
+                tiles.push_back(HistTile{l, txi, (int32_t)m0, (int32_t)std::min(M, m0 + step)});
+        }
+    }
+    MR1L_HIP_TRY(P->hist.upload(tiles.data(), tiles.size() * sizeof(HistTile)));
+    MR1L_HIP_TRY(P->res32.alloc((size_t)std::max<int64_t>(1, (int64_t)max_nlat * n) * sizeof(int32_t)));
     MR1L_HIP_TRY(P->bitmaps.alloc((size_t)std::max<int64_t>(1, P->bm_total) * sizeof(uint32_t)));
     MR1L_HIP_TRY(P->filt.alloc((size_t)std::max<int64_t>(1, P->filt_total) * sizeof(cx<T>)));
     MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->n_rhs) * sizeof(cx<T>)));
@@ -215,6 +233,9 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     a.work_stride = P->work_stride;
     a.bitmaps = P->bitmaps.as<uint32_t>();
     a.bm_total = P->bm_total;
+    a.res32 = P->res32.as<int32_t>();
+    a.hist = P->hist.as<HistTile>();
+    a.nhist = (int)tiles.size();
     a.large = P->large.as<int>();
     a.tile0_col = P->t0c.as<int>();
     a.tile0_row = P->t0r.as<int>();
@@ -290,12 +311,9 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = p->filt.as<cx<T>>();
     StageTimer tm(p, s);
-    if (!eval) {
-        tm.begin(0);
-        launch_clear_u32<T>(a.bitmaps, a.bm_total, s);
-        launch_residue_hist<T>(a, s);
-        tm.end();
-    }
+    tm.begin(0);
+    launch_alias(a, !eval, s);
+    tm.end();
     if (a.nsmall) {
         tm.begin(1);
         launch_bluestein_small<T>(a, y, a.samp_stride, true, work, filt, work, a.work_stride, false, -1, !eval, s);
@@ -326,12 +344,9 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = p->filt.as<cx<T>>();
     StageTimer tm(p, s);
-    if (!eval) {
-        tm.begin(0);
-        launch_clear_u32<T>(a.bitmaps, a.bm_total, s);
-        launch_residue_hist<T>(a, s);
-        tm.end();
-    }
+    tm.begin(0);
+    launch_alias(a, !eval, s);
+    tm.end();
     tm.begin(6);
     launch_clear_bins<T>(a, work, s);
     launch_scatter<T>(a, c, work, eval, s);
@@ -367,8 +382,7 @@ mr1l_status plan_adjoint(Plan* p, const void* coeffs, void* samples, hipStream_t
 }
 
 mr1l_status plan_alias(Plan* p, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s) {
-    launch_clear_u32<float>(p->args.bitmaps, p->args.bm_total, s);
-    launch_residue_hist<float>(p->args, s);
+    launch_alias(p->args, true, s);
     launch_alias_export(p->args, res, uniq, counter, s);
     MR1L_HIP_TRY(hipGetLastError());
     return MR1L_OK;

@@ -118,7 +118,7 @@ struct Plan {
     int64_t work_stride = 0;
     int64_t filt_total = 0;
     int64_t bm_total = 0;
-    DevMem freqs, desc, tx, tx_foff, z, bitmaps, filt, work, large, small, t0c, t0r;
+    DevMem freqs, desc, tx, tx_foff, z, bitmaps, filt, work, large, small, t0c, t0r, res32, hist;
     TxArgs args{};
     // per-stage timing
     bool timing = false;
