@@ -136,8 +136,10 @@ class SfftResult:
 
 
 def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = None,
-         r: int = 1, b: int = 10, seed: int = 0, tier: int = 1) -> SfftResult:
-    """Alg. 3 on the box search space [box_lo, box_hi] (inclusive, per component)."""
+         r: int = 1, b: int = 10, seed: int = 0, tier: int = 1, zero_anchors: bool = False) -> SfftResult:
+    """Alg. 3 on the box search space [box_lo, box_hi] (inclusive, per component).
+    ``zero_anchors``: anchor components fixed to 0 instead of drawn (the r = 1 setting of the
+    remark on coefficients with a common sign of real or imaginary part, Sec. 3.1)."""
     lo = np.asarray(box_lo, np.int64)
     hi = np.asarray(box_hi, np.int64)
     d = len(lo)
@@ -150,7 +152,7 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
         last = None
         for i in range(1, r + 1):
             k1 = R.key(seed, R.ANCHOR1D, t, i)
-            anchors = np.array([R.uniform01(k1, c) for c in range(d)])
+            anchors = np.zeros(d) if zero_anchors else np.array([R.uniform01(k1, c) for c in range(d)])
             y = black_box.sample_1d(t, i, anchors, K)
             pt = projection_1d(y, int(lo[t - 1]), int(hi[t - 1]))
             flags[select_top(pt, delta, s_local)] = True
@@ -182,7 +184,7 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
         flags = np.zeros(J.shape[0], bool)
         for i in range(1, r_t + 1):
             k1 = R.key(seed, R.ANCHOR, t, i)
-            tail = np.array([R.uniform01(k1, c) for c in range(t, d)])
+            tail = np.zeros(d - t) if zero_anchors else np.array([R.uniform01(k1, c) for c in range(t, d)])
             y = black_box.sample_lattice(t, i, M, z, tail, tier=tier)
             pt = forward(J, M, z, y) if tier == 1 else forward_direct(J, M, z, y)
             flags[select_top(pt, delta, s_t)] = True

@@ -216,7 +216,19 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     MR1L_HIP_TRY(P->hist.upload(tiles.data(), tiles.size() * sizeof(HistTile)));
     MR1L_HIP_TRY(P->res32.alloc((size_t)std::max<int64_t>(1, (int64_t)max_nlat * n) * sizeof(int32_t)));
     MR1L_HIP_TRY(P->bitmaps.alloc((size_t)std::max<int64_t>(1, P->bm_total) * sizeof(uint32_t)));
-    MR1L_HIP_TRY(P->filt.alloc((size_t)std::max<int64_t>(1, P->filt_total) * sizeof(cx<T>)));
+    const Plan* sh = sp.share_filters;
+    if (sh) {
+        bool same = sh->dtype == sp.dtype && sh->L == L;
+        for (int l = 0; same && l < L; ++l) same = sh->hdesc[l].M == P->hdesc[l].M;
+        if (!same) {
+            set_error("share_filters: lattice sizes or dtype differ");
+            return MR1L_ERR_ARG;
+        }
+        P->filt_ptr = sh->filt_ptr;
+    } else {
+        MR1L_HIP_TRY(P->filt.alloc((size_t)std::max<int64_t>(1, P->filt_total) * sizeof(cx<T>)));
+        P->filt_ptr = P->filt.p;
+    }
     MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->n_rhs) * sizeof(cx<T>)));
 
     TxArgs& a = P->args;
@@ -249,7 +261,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         set_error("could not allocate twiddle tables");
         return MR1L_ERR_NOMEM;
     }
-    build_filters<T>(P->hdesc.data(), L, a.desc, P->filt.as<cx<T>>(), P->filt_total, sp.device, nullptr);
+    if (!sh) build_filters<T>(P->hdesc.data(), L, a.desc, (cx<T>*)P->filt_ptr, P->filt_total, sp.device, nullptr);
     MR1L_HIP_TRY(hipGetLastError());
     MR1L_HIP_TRY(hipDeviceSynchronize());
     *out = guard.release();
@@ -309,7 +321,7 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
     const TxArgs& a = p->args;
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
-    const cx<T>* filt = p->filt.as<cx<T>>();
+    const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
     tm.begin(0);
     launch_alias(a, !eval, s);
@@ -342,7 +354,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
     const TxArgs& a = p->args;
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
-    const cx<T>* filt = p->filt.as<cx<T>>();
+    const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
     tm.begin(0);
     launch_alias(a, !eval, s);

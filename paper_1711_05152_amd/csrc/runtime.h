@@ -31,6 +31,20 @@ struct DevMem {
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
+    DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    DevMem& operator=(DevMem&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
     ~DevMem() { release(); }
     void release() {
         if (p) hipFree(p);
@@ -96,6 +110,8 @@ struct PlanSpec {
     int dev_ktype = K_I32;
     int64_t dev_maxabs = 0;            // max |k| of the device frequencies
     bool check_distinct = true;
+    // reuse the filter spectra of a plan with the same lattice sizes (same order) and dtype
+    const struct Plan* share_filters = nullptr;
     // transforms
     std::vector<int64_t> tx_n;         // frequencies per transform
     std::vector<int32_t> tx_L;         // lattices per transform
@@ -119,6 +135,7 @@ struct Plan {
     int64_t filt_total = 0;
     int64_t bm_total = 0;
     DevMem freqs, desc, tx, tx_foff, z, bitmaps, filt, work, large, small, t0c, t0r, res32, hist;
+    void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};
     // per-stage timing
     bool timing = false;

@@ -1,0 +1,101 @@
+"""Python binding of sfft_detect (Alg. 3) and of the built-in planted black box.
+
+Argument marshalling only: the 1-D projections, Alg. 1, the transforms, the selection and the
+compaction all run in libmr1l on the device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+__all__ = ["sfft_detect", "SfftResult"]
+
+
+@dataclass
+class SfftResult:
+    freqs: np.ndarray          # int32 [m, d], lexicographically ascending
+    coeffs: np.ndarray         # complex128 [m]
+    status: int
+    stats: dict = field(default_factory=dict)
+
+
+def _stats_dict(st: _lib.SfftStats) -> dict:
+    d = st.d
+    return {
+        "n_It": list(st.n_It[:d]), "n_J": list(st.n_J[:d]), "n_detected": list(st.n_detected[:d]),
+        "L": list(st.L[:d]), "sumM": list(st.sumM[:d]), "calls": list(st.calls[:d]),
+        "uncovered": list(st.uncovered[:d]), "samples": st.samples, "samples_full": st.samples_full,
+        "ms_sampling": st.ms_sampling, "ms_transform": st.ms_transform, "ms_construct": st.ms_construct,
+        "ms_select": st.ms_select, "ms_total": st.ms_total,
+    }
+
+
+class _CudaArray:
+    """__cuda_array_interface__ view of a device buffer (for caller-supplied samplers)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 3, "strides": None, "stream": None}
+
+
+def sfft_detect(lo, hi, *, planted=None, sampler=None, delta: float, s: int, s_local: int = 0, r: int = 1,
+                b: int = 10, seed: int = 0, dtype: str = "c64", zero_anchors: bool = False,
+                cap: int | None = None, device: int = 0, c: float = 2.0, gamma: float = 0.5) -> SfftResult:
+    """Alg. 3 on the box [lo, hi].
+
+    planted: (freqs int [s, d], coeffs complex [s], sigma, noise_seed) -- built-in black box;
+    sampler: callable(nodes: torch.Tensor float64 [n, d] on the device) -> torch.Tensor complex [n]
+             (used when planted is None)."""
+    lo = np.ascontiguousarray(np.asarray(lo, np.int32))
+    hi = np.ascontiguousarray(np.asarray(hi, np.int32))
+    d = int(lo.shape[0])
+    cap = int(s if cap is None else cap)
+    prm = _lib.SfftParams(delta=float(delta), s=int(s), s_local=int(s_local), r=int(r), b=int(b),
+                          seed=int(seed) & ((1 << 64) - 1), dtype={"c64": _lib.C64, "c128": _lib.C128}[dtype],
+                          c=float(c), gamma=float(gamma), zero_anchors=int(bool(zero_anchors)))
+    keep = []
+    pl_ptr = None
+    if planted is not None:
+        pf, pc, sigma, nseed = planted
+        pf = np.ascontiguousarray(np.asarray(pf, np.int32).reshape(-1, d))
+        pcc = np.ascontiguousarray(np.stack([np.real(pc), np.imag(pc)], axis=-1).astype(np.float64))
+        keep += [pf, pcc]
+        pl = _lib.SfftPlanted(s=int(pf.shape[0]), freqs=pf.ctypes.data, coeffs=pcc.ctypes.data, sigma=float(sigma),
+                              noise_seed=int(nseed) & ((1 << 64) - 1))
+        pl_ptr = C.pointer(pl)
+        cb = _lib.SAMPLER_FN()
+    else:
+        if sampler is None:
+            raise ValueError("need planted or sampler")
+        import torch
+        tdt = {"c64": torch.complex64, "c128": torch.complex128}[dtype]
+
+        def _cb(user, dd, n, nodes_ptr, values_ptr, stream):
+            try:
+                dev = torch.device("cuda", device)
+                x = torch.as_tensor(_CudaArray(nodes_ptr, (n, dd), "<f8"), device=dev)
+                out = torch.as_tensor(_CudaArray(values_ptr, (n, 2), "<f8" if dtype == "c128" else "<f4"),
+                                      device=dev)
+                v = sampler(x).to(tdt)
+                out.copy_(torch.view_as_real(v))
+                torch.cuda.synchronize(dev)
+                return 0
+            except Exception:  # reported as MR1L_ERR_CALLBACK
+                return 1
+        cb = _lib.SAMPLER_FN(_cb)
+        keep.append(cb)
+    f_out = np.zeros((max(1, cap), d), np.int32)
+    c_out = np.zeros((max(1, cap), 2), np.float64)
+    n_out = C.c_int64(0)
+    st = _lib.SfftStats()
+    status = lib().sfft_detect(d, lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p), cb, None, pl_ptr,
+                               C.byref(prm), cap, C.byref(n_out), f_out.ctypes.data_as(C.c_void_p),
+                               c_out.ctypes.data_as(C.c_void_p), C.byref(st), device)
+    check(status, "sfft_detect")
+    m = int(n_out.value)
+    return SfftResult(f_out[:m].copy(), c_out[:m, 0] + 1j * c_out[:m, 1], status, _stats_dict(st))

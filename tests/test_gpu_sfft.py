@@ -1,0 +1,128 @@
+"""GPU parity of sfft_detect (Alg. 3 on the device) against the CPU oracle.
+
+Detected frequency sets, per-step lattice sizes and sample counts must be bit-identical to the
+oracle run with the same seed (same SplitMix64 streams on both sides); coefficients follow the
+precision of the transforms.  The full-size d = 20 workload is checked through properties that
+hold at any size (exact support recovery, coefficient error against the planted values).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import require_gpu, assert_close
+from oracle.sfft import sfft as oracle_sfft, PlantedBlackBox
+from workloads import rng_for, random_planted, planted_c1, planted_c3
+
+pytestmark = pytest.mark.gpu
+
+SEED1 = 1711051521
+
+
+def _lex(f):
+    return np.lexsort(np.asarray(f).T[::-1])
+
+
+def _run(p, dtype, delta, s, r, b=10, seed=SEED1, s_local=0, zero_anchors=False):
+    from paper_1711_05152_amd.sfft import sfft_detect
+    return sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed), delta=delta, s=s,
+                       s_local=s_local, r=r, b=b, seed=seed, dtype=dtype, zero_anchors=zero_anchors, cap=max(s, 1))
+
+
+def _compare_with_oracle(p, dtype, delta, s, r, b=10, seed=SEED1, s_local=0, zero_anchors=False):
+    got = _run(p, dtype, delta, s, r, b, seed, s_local, zero_anchors)
+    bb = PlantedBlackBox(p.freqs, p.coeffs, p.sigma, p.noise_seed)
+    ref = oracle_sfft(p.lo, p.hi, bb, delta, s, s_local if s_local else s, r=r, b=b, seed=seed,
+                      zero_anchors=zero_anchors)
+    assert np.array_equal(got.freqs, ref.freqs), (got.freqs.shape, ref.freqs.shape)
+    st = got.stats
+    for step in ref.steps[1:]:
+        t = step["t"]
+        assert st["L"][t - 1] == step["L"], t
+        assert st["sumM"][t - 1] == step["sumM"], t
+        assert st["calls"][t - 1] == step["calls"], t
+        assert st["n_J"][t - 1] == step["n_J"], t
+    assert st["samples"] == ref.samples
+    assert_close(got.coeffs, ref.coeffs, dtype, "sfft coefficients vs oracle")
+    return got, ref
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_plain_d5_box8_s50(dtype):
+    """d = 5, box [-8,8]^5, s = 50 unit-modulus coefficients, r = 1, delta = 1e-12 (complex128
+    is the plain form; complex64 run for parity of the single-precision path)."""
+    require_gpu()
+    p = planted_c1()
+    delta = 1e-12 if dtype == "c128" else 1e-4
+    got, ref = _compare_with_oracle(p, dtype, delta, 50, 1)
+    order = _lex(p.freqs)
+    assert np.array_equal(got.freqs, p.freqs[order])
+    if dtype == "c128":
+        assert np.abs(got.coeffs - p.coeffs[order]).max() <= 1e-11
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_noisy_repetitions_parity(dtype):
+    """r = 3 detection iterations with complex Gaussian noise (Sec. 5.2 noise model)."""
+    require_gpu()
+    p = random_planted(rng_for(400), 5, 10, 120, "u1_10", sigma=1e-2, noise_seed=77)
+    _compare_with_oracle(p, dtype, 1e-3 if dtype == "c128" else 2e-3, 120, 3, seed=5)
+
+
+def test_selection_binds_s_local():
+    """s_local smaller than the number of candidates above delta: top-s selection with ties by
+    position decides the sets (same decision on both sides)."""
+    require_gpu()
+    p = random_planted(rng_for(401), 4, 6, 60, "u1_10")
+    _compare_with_oracle(p, "c128", 1e-9, 40, 2, s_local=25, seed=6)
+
+
+def test_zero_anchors_d1_and_empty():
+    require_gpu()
+    from paper_1711_05152_amd.sfft import sfft_detect
+    # real parts of one sign: the r = 1 setting with anchors fixed to 0
+    rng = rng_for(402)
+    p = random_planted(rng, 4, 5, 30, "unit")
+    p.coeffs = np.abs(p.coeffs.real) + 0.1 + 1j * p.coeffs.imag
+    _compare_with_oracle(p, "c128", 1e-9, 30, 1, zero_anchors=True, seed=7)
+    # d = 1
+    p1 = random_planted(rng, 1, 20, 6, "unit")
+    _compare_with_oracle(p1, "c128", 1e-9, 6, 2, seed=8)
+    # empty black box -> empty output
+    res = sfft_detect([-3, -3, -3], [3, 3, 3], planted=(np.zeros((0, 3), np.int32), np.zeros(0), 0.0, 0),
+                      delta=1e-6, s=10, r=1, b=3, seed=1)
+    assert res.freqs.shape == (0, 3)
+
+
+def test_callback_sampler_matches_planted():
+    """A caller-supplied black box (explicit nodes, evaluated here with torch on the device)
+    detects the same set as the built-in planted black box."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = random_planted(rng_for(403), 4, 5, 25, "unit")
+    hf = torch.tensor(p.freqs, dtype=torch.float64, device="cuda:0")
+    hc = torch.tensor(p.coeffs, dtype=torch.complex128, device="cuda:0")
+
+    def sampler(x):
+        ph = (x @ hf.T) % 1.0
+        return torch.exp(2j * np.pi * ph) @ hc
+
+    cb = sfft_detect(p.lo, p.hi, sampler=sampler, delta=1e-9, s=25, r=1, b=10, seed=9, dtype="c128")
+    pl = _run(p, "c128", 1e-9, 25, 1, seed=9)
+    assert np.array_equal(cb.freqs, pl.freqs)
+    assert np.abs(cb.coeffs - pl.coeffs).max() < 1e-10
+    assert np.array_equal(cb.freqs, p.freqs[_lex(p.freqs)])
+
+
+@pytest.mark.parametrize("sigma", [0.0, 1e-2])
+def test_scale_d20_box32_s1000(sigma):
+    """d = 20, box [-32,32]^20, s = 1000, |c| in [1,10], r = 5, delta = 1e-3, complex64 transforms:
+    exact support recovery (no false positives, no misses) and coefficient error against the
+    planted values within the noise level."""
+    require_gpu()
+    p = planted_c3(sigma)
+    got = _run(p, "c64", 1e-3, 1000, 5, seed=1711051523)
+    order = _lex(p.freqs)
+    assert np.array_equal(got.freqs, p.freqs[order])
+    err = np.abs(got.coeffs - p.coeffs[order])
+    print(f"sigma {sigma}: max coeff err {err.max():.3e}, samples {got.stats['samples']}, "
+          f"ms {got.stats['ms_total']:.1f}", flush=True)
+    assert err.max() <= (1e-4 * 10 if sigma == 0 else 1e-3)
