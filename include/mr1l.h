@@ -33,11 +33,11 @@ extern "C" {
 typedef enum mr1l_status {
     MR1L_OK = 0,
     MR1L_ERR_ARG = 1,          /* invalid argument (sizes, pointers, duplicate frequencies ...) */
-    MR1L_ERR_OVERFLOW = 2,     /* d * max|k| * max M_l too large for exact int64 residues      */
+    MR1L_ERR_OVERFLOW = 2,     /* d * max|k| * max M_l >= 2^62 (exact int64 residues)         */
     MR1L_ERR_NOMEM = 3,        /* device or host allocation failed                              */
     MR1L_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed                    */
     MR1L_ERR_CALLBACK = 5,     /* the user sampler returned non-zero                            */
-    MR1L_ERR_UNSUPPORTED = 6,  /* valid but outside this build's limits (e.g. M_l >= 2^31)      */
+    MR1L_ERR_UNSUPPORTED = 6,  /* valid but outside this build's limits (e.g. M_l >= 2^23)      */
     MR1L_WARN_UNCOVERED = 16   /* result defined, but some frequency lies in no I_l            */
 } mr1l_status;
 
@@ -60,7 +60,7 @@ typedef struct mr1l_plan_s* mr1l_plan_t;
 /* Build a transform plan (Alg. 2, inputs I and Lambda; Sec. 2.1 for the lattice definition).
  *   d, n        dimension (1..64) and number of frequencies (n >= 0)
  *   freqs       host int32 [n][d], pairwise distinct rows (checked)
- *   L, M, z     host int64 [L] lattice sizes (1 <= M_l < 2^31) and [L][d] generating vectors
+ *   L, M, z     host int64 [L] lattice sizes (1 <= M_l < 2^23) and [L][d] generating vectors
  *   dtype       precision of samples, coefficients and arithmetic
  *   weights     MR1L_W_PAPER or MR1L_W_EVAL (see above)
  *   n_rhs       number of right-hand sides transformed per call (>= 1)
@@ -68,12 +68,29 @@ typedef struct mr1l_plan_s* mr1l_plan_t;
  *   out         receives the plan; released with mr1l_destroy
  * The plan allocates its device scratch (packed frequencies, alias bitmaps, Bluestein filter
  * spectra, work area) and computes the filter spectra on the device; it synchronizes the device
- * before returning.  Errors: MR1L_ERR_ARG (bad sizes/pointers, duplicate rows),
- * MR1L_ERR_OVERFLOW (d * max|k| * max M_l >= 2^52), MR1L_ERR_UNSUPPORTED (M_l >= 2^31),
- * MR1L_ERR_NOMEM, MR1L_ERR_HIP. */
+ * before returning.  Residues are exact: the int64 dot products k.z_l never overflow because the
+ * plan rejects d * max|k| * max M_l >= 2^62 (MR1L_ERR_OVERFLOW; unreachable with int32 k,
+ * d <= 64 and M_l < 2^23).  Errors: MR1L_ERR_ARG (bad sizes/pointers, duplicate rows),
+ * MR1L_ERR_OVERFLOW, MR1L_ERR_UNSUPPORTED (M_l >= 2^23), MR1L_ERR_NOMEM, MR1L_ERR_HIP.
+ * The Bluestein work area is bounded (4 GiB); larger n_rhs are processed in chunks of
+ * right-hand sides within one call. */
 mr1l_status mr1l_plan(int d, int64_t n, const int32_t* freqs, int L, const int64_t* M,
                       const int64_t* z, mr1l_dtype dtype, mr1l_weights weights, int64_t n_rhs,
                       int device, mr1l_plan_t* out);
+
+/* Batched plan: n_tx independent transforms in one plan (each with its own frequency set and its
+ * own lattices, Alg. 2 applied to each), executed by the same few kernel launches per call.
+ *   n         host int64 [n_tx]: frequencies of transform b
+ *   freqs     host int32 [sum n][d]: the frequency sets one after another
+ *   L         host int32 [n_tx]: lattices of transform b
+ *   M, z      host int64 [sum L] and [sum L][d]: the lattices one transform after another
+ * Samples of one right-hand side are all lattices of all transforms one after another
+ * (transform-major); coefficients are all frequencies one after another.  Everything else as in
+ * mr1l_plan; mr1l_forward / mr1l_adjoint / mr1l_alias / mr1l_info accept batched plans (the alias
+ * export uses rows [j][sum n] for the j-th lattice of each frequency's own transform). */
+mr1l_status mr1l_plan_batched(int d, int n_tx, const int64_t* n, const int32_t* freqs, const int32_t* L,
+                              const int64_t* M, const int64_t* z, mr1l_dtype dtype, mr1l_weights weights,
+                              int64_t n_rhs, int device, mr1l_plan_t* out);
 
 /* Forward transform (Alg. 2; the residues k.z_l mod M_l, the alias histograms, the prime-length
  * DFTs and the gather are all recomputed on every call).

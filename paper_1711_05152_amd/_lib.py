@@ -15,7 +15,7 @@ NSTAGES = 8
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OVERFLOW", 3: "ERR_NOMEM", 4: "ERR_HIP", 5: "ERR_CALLBACK",
           6: "ERR_UNSUPPORTED", 16: "WARN_UNCOVERED"}
 
-EXPORTED = ["mr1l_plan", "mr1l_forward", "mr1l_adjoint", "mr1l_alias", "mr1l_info", "mr1l_destroy",
+EXPORTED = ["mr1l_plan", "mr1l_plan_batched", "mr1l_forward", "mr1l_adjoint", "mr1l_alias", "mr1l_info", "mr1l_destroy",
             "mr1l_timing_enable", "mr1l_timing_read", "mr1l_construct", "sfft_detect",
             "mr1l_last_error", "mr1l_version"]
 
@@ -66,6 +66,7 @@ def lib() -> C.CDLL:
     i32, i64, u64, vp, dbl = C.c_int, C.c_int64, C.c_uint64, C.c_void_p, C.c_double
     sig = {
         "mr1l_plan": [i32, i64, vp, i32, vp, vp, i32, i32, i64, i32, C.POINTER(vp)],
+        "mr1l_plan_batched": [i32, i32, vp, vp, vp, vp, vp, i32, i32, i64, i32, C.POINTER(vp)],
         "mr1l_forward": [vp, vp, vp, vp],
         "mr1l_adjoint": [vp, vp, vp, vp],
         "mr1l_alias": [vp, vp, vp, vp, vp],

@@ -229,7 +229,11 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         MR1L_HIP_TRY(P->filt.alloc((size_t)std::max<int64_t>(1, P->filt_total) * sizeof(cx<T>)));
         P->filt_ptr = P->filt.p;
     }
-    MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->n_rhs) * sizeof(cx<T>)));
+    {
+        const int64_t per_rhs = std::max<int64_t>(1, P->work_stride) * (int64_t)sizeof(cx<T>);
+        P->rhs_chunk = std::max<int64_t>(1, std::min<int64_t>(P->n_rhs, sp.max_work_bytes / per_rhs));
+    }
+    MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->rhs_chunk) * sizeof(cx<T>)));
 
     TxArgs& a = P->args;
     a.desc = P->desc.as<LatDesc>();
@@ -240,7 +244,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     a.max_nlat = max_nlat;
     a.z = P->z.as<int64_t>();
     a.n = n;
-    a.n_rhs = P->n_rhs;
+    a.n_rhs = P->rhs_chunk;
     a.samp_stride = P->sum_M;
     a.work_stride = P->work_stride;
     a.bitmaps = P->bitmaps.as<uint32_t>();
@@ -318,66 +322,76 @@ struct StageTimer {
 
 template <typename T>
 static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
-    const TxArgs& a = p->args;
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
     tm.begin(0);
-    launch_alias(a, !eval, s);
+    launch_alias(p->args, !eval, s);
     tm.end();
-    if (a.nsmall) {
-        tm.begin(1);
-        launch_bluestein_small<T>(a, y, a.samp_stride, true, work, filt, work, a.work_stride, false, -1, !eval, s);
+    for (int64_t r0 = 0; r0 < p->n_rhs; r0 += p->rhs_chunk) {
+        TxArgs a = p->args;
+        a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
+        const cx<T>* yc = y + r0 * a.samp_stride;
+        cx<T>* cc = c + r0 * a.n;
+        if (a.nsmall) {
+            tm.begin(1);
+            launch_bluestein_small<T>(a, yc, a.samp_stride, true, work, filt, work, a.work_stride, false, -1, !eval, s);
+            tm.end();
+        }
+        if (a.nlarge) {
+            tm.begin(2);
+            launch_p1<T>(a, yc, a.samp_stride, true, work, -1, s);
+            tm.end();
+            tm.begin(3);
+            launch_p2<T>(a, work, filt, -1, s);
+            tm.end();
+            tm.begin(4);
+            launch_p3<T>(a, work, work, a.work_stride, false, -1, !eval, s);
+            tm.end();
+        }
+        tm.begin(5);
+        launch_gather<T>(a, work, cc, eval, s);
         tm.end();
     }
-    if (a.nlarge) {
-        tm.begin(2);
-        launch_p1<T>(a, y, a.samp_stride, true, work, -1, s);
-        tm.end();
-        tm.begin(3);
-        launch_p2<T>(a, work, filt, -1, s);
-        tm.end();
-        tm.begin(4);
-        launch_p3<T>(a, work, work, a.work_stride, false, -1, !eval, s);
-        tm.end();
-    }
-    tm.begin(5);
-    launch_gather<T>(a, work, c, eval, s);
-    tm.end();
     MR1L_HIP_TRY(hipGetLastError());
     return MR1L_OK;
 }
 
 template <typename T>
 static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
-    const TxArgs& a = p->args;
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
     tm.begin(0);
-    launch_alias(a, !eval, s);
+    launch_alias(p->args, !eval, s);
     tm.end();
-    tm.begin(6);
-    launch_clear_bins<T>(a, work, s);
-    launch_scatter<T>(a, c, work, eval, s);
-    tm.end();
-    if (a.nsmall) {
-        tm.begin(1);
-        launch_bluestein_small<T>(a, work, a.work_stride, false, work, filt, y, a.samp_stride, true, +1, !eval, s);
+    for (int64_t r0 = 0; r0 < p->n_rhs; r0 += p->rhs_chunk) {
+        TxArgs a = p->args;
+        a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
+        const cx<T>* cc = c + r0 * a.n;
+        cx<T>* yc = y + r0 * a.samp_stride;
+        tm.begin(6);
+        launch_clear_bins<T>(a, work, s);
+        launch_scatter<T>(a, cc, work, eval, s);
         tm.end();
-    }
-    if (a.nlarge) {
-        tm.begin(2);
-        launch_p1<T>(a, work, a.work_stride, false, work, +1, s);
-        tm.end();
-        tm.begin(3);
-        launch_p2<T>(a, work, filt, +1, s);
-        tm.end();
-        tm.begin(4);
-        launch_p3<T>(a, work, y, a.samp_stride, true, +1, !eval, s);
-        tm.end();
+        if (a.nsmall) {
+            tm.begin(1);
+            launch_bluestein_small<T>(a, work, a.work_stride, false, work, filt, yc, a.samp_stride, true, +1, !eval, s);
+            tm.end();
+        }
+        if (a.nlarge) {
+            tm.begin(2);
+            launch_p1<T>(a, work, a.work_stride, false, work, +1, s);
+            tm.end();
+            tm.begin(3);
+            launch_p2<T>(a, work, filt, +1, s);
+            tm.end();
+            tm.begin(4);
+            launch_p3<T>(a, work, yc, a.samp_stride, true, +1, !eval, s);
+            tm.end();
+        }
     }
     MR1L_HIP_TRY(hipGetLastError());
     return MR1L_OK;
@@ -441,6 +455,47 @@ mr1l_status mr1l_plan(int d, int64_t n, const int32_t* freqs, int L, const int64
     sp.tx_L = {L};
     sp.M.assign(M, M + L);
     sp.z.assign(z, z + (size_t)L * (d > 0 ? d : 0));
+    Plan* p = nullptr;
+    mr1l_status st = plan_create(sp, &p);
+    if (st == MR1L_OK) *out = (mr1l_plan_t)p;
+    return st;
+    MR1L_GUARD_END
+}
+
+mr1l_status mr1l_plan_batched(int d, int n_tx, const int64_t* n, const int32_t* freqs, const int32_t* L,
+                              const int64_t* M, const int64_t* z, mr1l_dtype dtype, mr1l_weights weights,
+                              int64_t n_rhs, int device, mr1l_plan_t* out) {
+    MR1L_GUARD_BEGIN
+    clear_error();
+    if (!out || n_tx < 1 || !n || !L || (dtype != MR1L_C64 && dtype != MR1L_C128) ||
+        (weights != MR1L_W_PAPER && weights != MR1L_W_EVAL) || d < 1 || d > 64) {
+        set_error("invalid argument to mr1l_plan_batched");
+        return MR1L_ERR_ARG;
+    }
+    int64_t ntot = 0, Ltot = 0;
+    for (int i = 0; i < n_tx; ++i) {
+        if (n[i] < 0 || L[i] < 0) {
+            set_error("negative size in mr1l_plan_batched");
+            return MR1L_ERR_ARG;
+        }
+        ntot += n[i];
+        Ltot += L[i];
+    }
+    if ((ntot > 0 && !freqs) || (Ltot > 0 && (!M || !z))) {
+        set_error("null array in mr1l_plan_batched");
+        return MR1L_ERR_ARG;
+    }
+    PlanSpec sp;
+    sp.d = d;
+    sp.dtype = dtype;
+    sp.weights = weights;
+    sp.n_rhs = n_rhs;
+    sp.device = device;
+    sp.host_freqs = freqs;
+    sp.tx_n.assign(n, n + n_tx);
+    sp.tx_L.assign(L, L + n_tx);
+    sp.M.assign(M, M + Ltot);
+    sp.z.assign(z, z + (size_t)Ltot * d);
     Plan* p = nullptr;
     mr1l_status st = plan_create(sp, &p);
     if (st == MR1L_OK) *out = (mr1l_plan_t)p;

@@ -110,6 +110,7 @@ struct PlanSpec {
     int dev_ktype = K_I32;
     int64_t dev_maxabs = 0;            // max |k| of the device frequencies
     bool check_distinct = true;
+    int64_t max_work_bytes = (int64_t)4 << 30;   // bound of the Bluestein work area (rhs chunking)
     // reuse the filter spectra of a plan with the same lattice sizes (same order) and dtype
     const struct Plan* share_filters = nullptr;
     // transforms
@@ -127,6 +128,7 @@ struct Plan {
     mr1l_dtype dtype = MR1L_C64;
     mr1l_weights weights = MR1L_W_PAPER;
     int64_t n_rhs = 1;
+    int64_t rhs_chunk = 1;             // right-hand sides per pass through the work area
     std::vector<LatDesc> hdesc;
     std::vector<TxDesc> htx;
     std::vector<int64_t> samp_off;     // [L + 1]

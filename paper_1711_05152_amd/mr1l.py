@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-__all__ = ["Plan", "mr1l_plan", "mr1l_construct", "version"]
+__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "version"]
 
 _DT = {"c64": (_lib.C64, torch.complex64), "c128": (_lib.C128, torch.complex128)}
 _W = {"paper": _lib.W_PAPER, "eval": _lib.W_EVAL}
@@ -43,6 +43,8 @@ class Plan:
         Mv = np.ascontiguousarray(np.asarray(M, dtype=np.int64).reshape(-1))
         zv = np.ascontiguousarray(np.asarray(z, dtype=np.int64).reshape(len(Mv), self.d))
         self.L = int(len(Mv))
+        self.M = Mv
+        self.z = zv
         self.dtype_name = dtype
         self.code, self.torch_dtype = _DT[dtype]
         self.weights = weights
@@ -55,14 +57,16 @@ class Plan:
                               Mv.ctypes.data_as(C.c_void_p), zv.ctypes.data_as(C.c_void_p), self.code,
                               _W[weights], self.n_rhs, self.device.index, C.byref(handle)), "mr1l_plan")
         self._h = handle
+        self.max_nlat = self.L
+        self._finish()
+
+    def _finish(self):
         off = np.zeros(self.L + 1, np.int64)
         lens = np.zeros(max(1, self.L), np.int64)
         check(lib().mr1l_info(self._h, off.ctypes.data_as(C.c_void_p), None, lens.ctypes.data_as(C.c_void_p)),
               "mr1l_info")
         self.sample_offsets = off
         self.fft_lengths = lens[: self.L]
-        self.M = Mv
-        self.z = zv
         self.sum_M = int(off[-1])
 
     # -- helpers ----------------------------------------------------------------------------------
@@ -100,8 +104,8 @@ class Plan:
 
     def alias(self):
         """mr1l_alias: (residues int64 [L, n], unaliased uint8 [L, n], counter uint8 [n]) on device."""
-        res = torch.empty((self.L, self.n), dtype=torch.int64, device=self.device)
-        uniq = torch.empty((self.L, self.n), dtype=torch.uint8, device=self.device)
+        res = torch.empty((self.max_nlat, self.n), dtype=torch.int64, device=self.device)
+        uniq = torch.empty((self.max_nlat, self.n), dtype=torch.uint8, device=self.device)
         cnt = torch.empty((self.n,), dtype=torch.uint8, device=self.device)
         check(lib().mr1l_alias(self._h, _ptr(res), _ptr(uniq), _ptr(cnt), _stream(self.device)), "mr1l_alias")
         return res, uniq, cnt
@@ -110,6 +114,21 @@ class Plan:
         u = C.c_int64(0)
         check(lib().mr1l_info(self._h, None, C.byref(u), None), "mr1l_info")
         return int(u.value)
+
+    # -- graph capture ----------------------------------------------------------------------------
+    def capture(self, direction: str, inp: torch.Tensor, out: torch.Tensor):
+        """Record one forward or adjoint call (its fixed set of kernel launches) into a HIP graph
+        through torch.cuda.CUDAGraph; replay() then reruns it on the same buffers."""
+        fn = self.forward if direction == "forward" else self.adjoint
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            fn(inp, out=out)
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn(inp, out=out)
+        return g
 
     # -- timing -----------------------------------------------------------------------------------
     def timing(self, enable: bool = True) -> None:
@@ -132,6 +151,43 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BatchedPlan(Plan):
+    """mr1l_plan_batched: independent transforms [(freqs_b, M_b, z_b), ...] in one plan; samples
+    and coefficients of the transforms are stacked one after another."""
+
+    def __init__(self, problems, dtype: str = "c64", weights: str = "paper", n_rhs: int = 1,
+                 device: int | torch.device | None = None):
+        d = int(np.asarray(problems[0][0]).shape[1])
+        fl = [np.asarray(p[0], np.int32).reshape(-1, d) for p in problems]
+        Ml = [np.asarray(p[1], np.int64).reshape(-1) for p in problems]
+        zl = [np.asarray(p[2], np.int64).reshape(len(m), d) for p, m in zip(problems, Ml)]
+        self.tx_n = np.array([f.shape[0] for f in fl], np.int64)
+        self.tx_L = np.array([len(m) for m in Ml], np.int32)
+        f = np.ascontiguousarray(np.concatenate(fl)) if len(fl) else np.zeros((0, d), np.int32)
+        Mv = np.ascontiguousarray(np.concatenate(Ml))
+        zv = np.ascontiguousarray(np.concatenate(zl))
+        self.n, self.d, self.L = int(f.shape[0]), d, int(len(Mv))
+        self.M, self.z = Mv, zv
+        self.dtype_name = dtype
+        self.code, self.torch_dtype = _DT[dtype]
+        self.weights = weights
+        self.n_rhs = int(n_rhs)
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        handle = C.c_void_p()
+        check(lib().mr1l_plan_batched(d, len(problems), self.tx_n.ctypes.data_as(C.c_void_p),
+                                      f.ctypes.data_as(C.c_void_p), self.tx_L.ctypes.data_as(C.c_void_p),
+                                      Mv.ctypes.data_as(C.c_void_p), zv.ctypes.data_as(C.c_void_p), self.code,
+                                      _W[weights], self.n_rhs, self.device.index, C.byref(handle)),
+              "mr1l_plan_batched")
+        self._h = handle
+        self.max_nlat = int(self.tx_L.max()) if len(self.tx_L) else 0
+        self.freq_offsets = np.concatenate([[0], np.cumsum(self.tx_n)])
+        self.lat_offsets = np.concatenate([[0], np.cumsum(self.tx_L)])
+        self._finish()
 
 
 def mr1l_plan(*args, **kwargs) -> Plan:
