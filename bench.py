@@ -36,7 +36,142 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sparse-FFT, batched and gradient-descent workloads")
+    ap.add_argument("--gd-steps", type=int, default=5)
     return ap.parse_args()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def extra_sfft():
+    """Sparse FFT solves (Alg. 3 on the device): repetitions batched as right-hand sides vs one
+    transform call per repetition ("plain")."""
+    import numpy as np
+    from paper_1711_05152_amd.sfft import sfft_detect
+    from workloads import planted_c1, planted_c3
+    out = {}
+    cases = [("d5_box8_s50_r1_c128", planted_c1(), "c128", 1e-12, 50, 1, 1711051521),
+             ("d20_box32_s1000_r5_c64", planted_c3(0.0), "c64", 1e-3, 1000, 5, 1711051523),
+             ("d20_box32_s1000_r5_c64_sigma1e-2", planted_c3(1e-2), "c64", 1e-3, 1000, 5, 1711051523)]
+    for name, p, dt, delta, s, r, seed in cases:
+        row = {}
+        for mode in ("batched", "plain"):
+            times, res = [], None
+            for _ in range(3):
+                res = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed), delta=delta,
+                                  s=s, r=r, b=10, seed=seed, dtype=dt, plain=(mode == "plain"))
+                times.append(res.stats["ms_total"])
+            order = np.lexsort(p.freqs.T[::-1])
+            ok = bool(np.array_equal(res.freqs, p.freqs[order]))
+            st = res.stats
+            row[mode] = {"ms_total_median": float(np.median(times)), "ms_excl_sampling": st["ms_total"] - st["ms_sampling"],
+                         "ms_sampling": st["ms_sampling"], "ms_transform": st["ms_transform"],
+                         "ms_construct": st["ms_construct"], "ms_select": st["ms_select"],
+                         "samples": st["samples"], "support_recovered": ok,
+                         "max_coeff_err": float(np.abs(res.coeffs - p.coeffs[order]).max()) if ok else None}
+        row["batched_over_plain_time"] = row["batched"]["ms_total_median"] / row["plain"]["ms_total_median"]
+        out[name] = row
+    return out
+
+
+def extra_batched():
+    """512 independent transforms (d=15, |I_b| log-uniform in [2^8,2^18], L_b = ceil(log2 |I_b|),
+    primes in [|I_b|, 2|I_b|]): one batched plan (eager and HIP-graph replay) vs one plan per
+    transform launched one after another.  Forward + adjoint per step."""
+    import numpy as np
+    import torch
+    from paper_1711_05152_amd.mr1l import BatchedPlan, Plan
+    from workloads import batched_c4
+    probs = batched_c4(with_data=False)
+    ntot = sum(p.n for p in probs)
+    g = torch.Generator(device="cuda:0").manual_seed(4)
+    bp = BatchedPlan([(p.freqs, p.M, p.z) for p in probs], dtype="c64", device=0)
+    y = torch.randn(bp.sum_M, dtype=torch.complex64, device="cuda:0", generator=g)[None, :]
+    c = torch.randn(bp.n, dtype=torch.complex64, device="cuda:0", generator=g)[None, :]
+    co, yo = bp.empty_coeffs(), bp.empty_samples()
+
+    def timeit(fn, reps=10):
+        fn()
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        _sync()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    t_batched = timeit(lambda: (bp.forward(y, out=co), bp.adjoint(c, out=yo)))
+    gf = bp.capture("forward", y, co)
+    ga = bp.capture("adjoint", c, yo)
+    t_graph = timeit(lambda: (gf.replay(), ga.replay()))
+    plans = [Plan(p.freqs, p.M, p.z, dtype="c64", device=0) for p in probs]
+    fo = np.concatenate([[0], np.cumsum([p.n for p in probs])])
+    so = np.concatenate([[0], np.cumsum([int(p.M.sum()) for p in probs])])
+    views = [(y[:, so[b]:so[b + 1]], c[:, fo[b]:fo[b + 1]], co[:, fo[b]:fo[b + 1]], yo[:, so[b]:so[b + 1]])
+             for b in range(len(probs))]
+    cos = [pl.empty_coeffs() for pl in plans]
+    yos = [pl.empty_samples() for pl in plans]
+    ys = [v[0].contiguous() for v in views]
+    cs = [v[1].contiguous() for v in views]
+
+    def plain():
+        for b, pl in enumerate(plans):
+            pl.forward(ys[b], out=cos[b])
+            pl.adjoint(cs[b], out=yos[b])
+    t_plain = timeit(plain, reps=3)
+    return {"transforms": len(probs), "sum_n": int(ntot), "sum_M": int(bp.sum_M),
+            "ms_fwd_adj_batched": t_batched, "ms_fwd_adj_batched_graph": t_graph, "ms_fwd_adj_plain": t_plain,
+            "freqs_per_s_batched_graph": ntot / (t_graph * 1e-3), "freqs_per_s_plain": ntot / (t_plain * 1e-3),
+            "plain_over_batched_graph": t_plain / t_graph}
+
+
+def extra_autograd(steps: int):
+    """Gradient descent on L(c) = 1/2 sum_l (1/M_l) ||A_l c - y_l||^2 with the differentiable
+    Fourier-matrix transform: |I| = 2^20 in [-16,16]^30, L = 20 primes in [2^20, 2^21], 64
+    right-hand sides, y = A c_true + complex Gaussian noise sigma = 1e-3, complex64."""
+    import numpy as np
+    import torch
+    from paper_1711_05152_amd.autograd import Mr1lSynth
+    from paper_1711_05152_amd.mr1l import Plan
+    from workloads import lsq_c5
+    freqs, M, z, seed = lsq_c5()
+    n_rhs = 64
+    ep = Plan(freqs, M, z, dtype="c64", weights="eval", n_rhs=n_rhs, device=0)
+    g = torch.Generator(device="cuda:0").manual_seed(seed % (1 << 62))
+    with torch.no_grad():
+        c_true = torch.randn((n_rhs, ep.n), dtype=torch.complex64, device="cuda:0", generator=g)
+        y = ep.adjoint(c_true)
+        y += 1e-3 * torch.randn(y.shape, dtype=torch.complex64, device="cuda:0", generator=g)
+        del c_true
+        res, _, _ = ep.alias()
+        step = 1.0 / sum(int(torch.bincount(res[l]).max()) for l in range(ep.L))
+        del res
+    w = torch.from_numpy(np.concatenate([np.full(int(m), 1.0 / m) for m in M]).astype(np.float32)).to("cuda:0")
+    c = torch.zeros((n_rhs, ep.n), dtype=torch.complex64, device="cuda:0", requires_grad=True)
+    losses = []
+
+    def gd_step():
+        r = Mr1lSynth.apply(c, ep) - y
+        loss = 0.5 * (w * (r.real ** 2 + r.imag ** 2)).sum()
+        c.grad = None
+        loss.backward()
+        with torch.no_grad():
+            c.sub_(step * c.grad)
+        return loss.detach()
+
+    losses.append(float(gd_step()))
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        losses.append(float(gd_step()))
+    _sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"n": ep.n, "d": 30, "L": ep.L, "n_rhs": n_rhs, "sum_M": ep.sum_M, "ms_per_gd_step": ms,
+            "steps_timed": steps, "loss_first": losses[0], "loss_last": losses[-1],
+            "loss_monotone": all(b <= a for a, b in zip(losses, losses[1:]))}
 
 
 def fft_flops(N: int) -> float:
@@ -179,6 +314,9 @@ def main():
         "stages_ms_per_launch": per_launch,
         "cpu_baseline": cpu,
     }
+    if not args.no_extras:
+        line["extra"] = {"sfft": extra_sfft(), "batched_512": extra_batched(),
+                         "autograd_lsq": extra_autograd(args.gd_steps)}
     print(json.dumps(line), flush=True)
 
 

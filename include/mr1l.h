@@ -179,6 +179,8 @@ typedef struct sfft_params {
     mr1l_dtype dtype;        /* precision of the transforms                      */
     double c, gamma;         /* Alg. 1 parameters (0 selects 2 and 1/2)          */
     int zero_anchors;        /* 1: anchors fixed to 0 (r = 1 mode of Sec. 3.1)   */
+    int plain;               /* 1: one transform call per repetition (no batching
+                                of repetitions / 1-D lines as right-hand sides)  */
 } sfft_params;
 
 #define SFFT_MAX_D 64

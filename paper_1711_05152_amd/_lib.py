@@ -37,7 +37,7 @@ class SfftPlanted(C.Structure):
 class SfftParams(C.Structure):
     _fields_ = [("delta", C.c_double), ("s", C.c_int64), ("s_local", C.c_int64), ("r", C.c_int),
                 ("b", C.c_int), ("seed", C.c_uint64), ("dtype", C.c_int), ("c", C.c_double),
-                ("gamma", C.c_double), ("zero_anchors", C.c_int)]
+                ("gamma", C.c_double), ("zero_anchors", C.c_int), ("plain", C.c_int)]
 
 
 SFFT_MAX_D = 64

@@ -95,7 +95,8 @@ mr1l_status detect_1d(Ctx& C, std::vector<DevMem>& It, std::vector<int64_t>& nIt
         sp.d = 1;
         sp.dtype = C.prm.dtype;
         sp.weights = MR1L_W_PAPER;
-        sp.n_rhs = njobs;
+        const int per_call = C.prm.plain ? 1 : njobs;
+        sp.n_rhs = per_call;
         sp.device = C.device;
         sp.host_freqs = f1.data();
         sp.check_distinct = false;
@@ -150,7 +151,9 @@ mr1l_status detect_1d(Ctx& C, std::vector<DevMem>& It, std::vector<int64_t>& nIt
 
         t0 = clk::now();
         MR1L_HIP_TRY(coeffs.alloc((size_t)njobs * K * csz));
-        TRY(plan_forward(pg.p, y.p, coeffs.p, C.st));
+        for (int q0 = 0; q0 < njobs; q0 += per_call)
+            TRY(plan_forward(pg.p, (const char*)y.p + (size_t)q0 * K * csz, (char*)coeffs.p + (size_t)q0 * K * csz,
+                             C.st));
         TRY(sync_check(C.st));
         if (C.stats) C.stats->ms_transform += ms_since(t0);
 
@@ -244,11 +247,12 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
         if (cr.uncovered) *uncovered_any = true;
         const int rt = t < d ? r : 1;
         const int64_t st_ = t < d ? C.prm.s_local : C.prm.s;
+        const int per_call = C.prm.plain ? 1 : rt;
         PlanSpec sp;
         sp.d = t;
         sp.dtype = C.prm.dtype;
         sp.weights = MR1L_W_PAPER;
-        sp.n_rhs = rt;
+        sp.n_rhs = per_call;
         sp.device = C.device;
         sp.dev_freqs = J.p;
         sp.dev_ktype = C.kt;
@@ -288,7 +292,7 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
                 pp.d = t;
                 pp.dtype = C.prm.dtype;
                 pp.weights = MR1L_W_EVAL;
-                pp.n_rhs = rt;
+                pp.n_rhs = per_call;
                 pp.device = C.device;
                 pp.dev_freqs = C.hf.p;           // first t components of [d][s]
                 pp.dev_ktype = K_I32;
@@ -304,7 +308,9 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
                 DevMem w;
                 MR1L_HIP_TRY(w.alloc((size_t)rt * C.s_pl * csz));
                 sf_planted_wlat(C.prm.dtype, C.hf.as<int32_t>(), C.s_pl, d, t, C.hc.p, dA.as<double>(), rt, w.p, C.st);
-                TRY(plan_adjoint(pP.p, w.p, y.p, C.st));
+                for (int i0 = 0; i0 < rt; i0 += per_call)
+                    TRY(plan_adjoint(pP.p, (const char*)w.p + (size_t)i0 * C.s_pl * csz,
+                                     (char*)y.p + (size_t)i0 * sumM * csz, C.st));
                 TRY(sync_check(C.st));
             } else {
                 MR1L_HIP_TRY(hipMemsetAsync(y.p, 0, (size_t)rt * sumM * csz, C.st));
@@ -338,7 +344,9 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
         t0 = clk::now();
         DevMem coeffs;
         MR1L_HIP_TRY(coeffs.alloc((size_t)rt * nJ * csz));
-        TRY(plan_forward(pJ.p, y.p, coeffs.p, C.st));
+        for (int i0 = 0; i0 < rt; i0 += per_call)
+            TRY(plan_forward(pJ.p, (const char*)y.p + (size_t)i0 * sumM * csz, (char*)coeffs.p + (size_t)i0 * nJ * csz,
+                             C.st));
         TRY(sync_check(C.st));
         if (C.stats) C.stats->ms_transform += ms_since(t0);
 

@@ -45,10 +45,12 @@ class _CudaArray:
 
 def sfft_detect(lo, hi, *, planted=None, sampler=None, delta: float, s: int, s_local: int = 0, r: int = 1,
                 b: int = 10, seed: int = 0, dtype: str = "c64", zero_anchors: bool = False,
-                cap: int | None = None, device: int = 0, c: float = 2.0, gamma: float = 0.5) -> SfftResult:
+                cap: int | None = None, device: int = 0, c: float = 2.0, gamma: float = 0.5,
+                plain: bool = False) -> SfftResult:
     """Alg. 3 on the box [lo, hi].
 
     planted: (freqs int [s, d], coeffs complex [s], sigma, noise_seed) -- built-in black box;
+    plain:   one transform call per repetition instead of repetitions as right-hand sides;
     sampler: callable(nodes: torch.Tensor float64 [n, d] on the device) -> torch.Tensor complex [n]
              (used when planted is None)."""
     lo = np.ascontiguousarray(np.asarray(lo, np.int32))
@@ -57,7 +59,8 @@ def sfft_detect(lo, hi, *, planted=None, sampler=None, delta: float, s: int, s_l
     cap = int(s if cap is None else cap)
     prm = _lib.SfftParams(delta=float(delta), s=int(s), s_local=int(s_local), r=int(r), b=int(b),
                           seed=int(seed) & ((1 << 64) - 1), dtype={"c64": _lib.C64, "c128": _lib.C128}[dtype],
-                          c=float(c), gamma=float(gamma), zero_anchors=int(bool(zero_anchors)))
+                          c=float(c), gamma=float(gamma), zero_anchors=int(bool(zero_anchors)),
+                          plain=int(bool(plain)))
     keep = []
     pl_ptr = None
     if planted is not None:

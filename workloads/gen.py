@@ -43,9 +43,19 @@ def primes_between(lo: int, hi: int) -> np.ndarray:
     return out[out >= lo].astype(np.int64)
 
 
+def _row_keys(rows: np.ndarray, lo: int) -> np.ndarray:
+    """64-bit polynomial hash of integer rows (distinct rows collide with probability ~2^-64)."""
+    h = np.zeros(rows.shape[0], np.uint64)
+    mult = np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        for c in range(rows.shape[1]):
+            h = h * mult + (rows[:, c].astype(np.int64) - lo).astype(np.uint64) + np.uint64(1)
+    return h
+
+
 def distinct_freqs(rng: np.random.Generator, n: int, d: int, lo: int, hi: int) -> np.ndarray:
     """n distinct integer vectors drawn uniformly without replacement from the box [lo, hi]^d,
-    returned in draw order as int32 [n, d]."""
+    returned in draw order as int32 [n, d] (later repeats of an earlier row are dropped)."""
     span = hi - lo + 1
     if n > span ** d:
         raise ValueError("box too small for the requested number of distinct frequencies")
@@ -56,7 +66,13 @@ def distinct_freqs(rng: np.random.Generator, n: int, d: int, lo: int, hi: int) -
         batch = rng.integers(lo, hi + 1, size=(max(64, 2 * (n - acc.shape[0])), d),
                              dtype=np.int64).astype(np.int32)
         allrows = np.concatenate([acc, batch])
-        _, first = np.unique(allrows, axis=0, return_index=True)
+        if span ** d <= (1 << 62):
+            keys = np.zeros(allrows.shape[0], np.int64)     # exact mixed-radix code of the row
+            for c in range(d):
+                keys = keys * span + (allrows[:, c].astype(np.int64) - lo)
+        else:
+            keys = _row_keys(allrows, lo)
+        _, first = np.unique(keys, return_index=True)
         acc = allrows[np.sort(first)]          # unique rows, in order of first draw
     return np.ascontiguousarray(acc[:n])
 
@@ -86,10 +102,12 @@ class TransformProblem:
 
 
 def transform_problem(rng: np.random.Generator, n: int, d: int, box: int, L: int,
-                      m_lo: int, m_hi: int, n_rhs: int = 1, prime: bool = True) -> TransformProblem:
+                      m_lo: int, m_hi: int, n_rhs: int = 1, prime: bool = True,
+                      with_data: bool = True) -> TransformProblem:
     """Frequencies uniform in [-box, box]^d without replacement; L distinct lattice sizes drawn
     uniformly among the primes (or all integers) in [m_lo, m_hi]; generators uniform in
-    [0, M_l - 1]^d; samples and coefficients CN(0,1)."""
+    [0, M_l - 1]^d; samples and coefficients CN(0,1) (left empty when ``with_data`` is False,
+    for consumers that draw them on the device)."""
     freqs = distinct_freqs(rng, n, d, -box, box)
     pool = primes_between(m_lo, m_hi) if prime else np.arange(m_lo, m_hi + 1, dtype=np.int64)
     if len(pool) < L:
@@ -97,8 +115,12 @@ def transform_problem(rng: np.random.Generator, n: int, d: int, box: int, L: int
     M = np.sort(rng.choice(pool, size=L, replace=False)).astype(np.int64)
     M = rng.permutation(M)
     z = np.stack([rng.integers(0, m, size=d, dtype=np.int64) for m in M]) if L else np.zeros((0, d), np.int64)
-    samples = cn01(rng, (n_rhs, int(M.sum())))
-    coeffs = cn01(rng, (n_rhs, n))
+    if with_data:
+        samples = cn01(rng, (n_rhs, int(M.sum())))
+        coeffs = cn01(rng, (n_rhs, n))
+    else:
+        samples = np.zeros((n_rhs, 0), np.complex128)
+        coeffs = np.zeros((n_rhs, 0), np.complex128)
     return TransformProblem(freqs, M, z.astype(np.int64), samples, coeffs)
 
 
@@ -164,7 +186,7 @@ def planted_c3(sigma: float = 0.0) -> PlantedPoly:
 
 
 def batched_c4(count: int = 512, d: int = 15, box: int = 32, seed_extra: int = 0,
-               log2_lo: float = 8.0, log2_hi: float = 18.0) -> list[TransformProblem]:
+               log2_lo: float = 8.0, log2_hi: float = 18.0, with_data: bool = True) -> list[TransformProblem]:
     """Batched workload: ``count`` independent transforms, |I_b| = round(2^U), U uniform in
     [log2_lo, log2_hi]; frequencies uniform in [-32,32]^15; L_b = ceil(log2 |I_b|) distinct
     primes uniform in [|I_b|, 2|I_b|]."""
@@ -173,7 +195,7 @@ def batched_c4(count: int = 512, d: int = 15, box: int = 32, seed_extra: int = 0
     for _ in range(count):
         n = int(round(2.0 ** rng.uniform(log2_lo, log2_hi)))
         L = int(math.ceil(math.log2(n)))
-        out.append(transform_problem(rng, n, d, box, L, n, 2 * n))
+        out.append(transform_problem(rng, n, d, box, L, n, 2 * n, with_data=with_data))
     return out
 
 
