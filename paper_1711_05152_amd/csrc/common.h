@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace mr1l {
 
 // ---- complex arithmetic ---------------------------------------------------------------------------
@@ -73,12 +75,25 @@ enum KType { K_I8 = 0, K_I16 = 1, K_I32 = 2 };
 
 constexpr int kThreads = 256;      // threads per workgroup of every FFT kernel
 constexpr int kSmallMaxLg = 12;    // one-block Bluestein up to 2^12 points
+constexpr int kMaxLgN = 24;        // largest Bluestein length 2^24 (M_l < 2^23)
 constexpr int kTwLg = 12;          // twiddle table e^{-2 pi i m / 4096}, m < 4096
+constexpr int kTileLg = 12;        // elements of one four-step tile (fp32 32 KiB, fp64 64 KiB of LDS)
 
-// Elements held in LDS by one four-step tile (fp32: 64 KiB, fp64: 64 KiB).
-template <typename T> struct TileElems;
-template <> struct TileElems<float> { static constexpr int lg = 12; };
-template <> struct TileElems<double> { static constexpr int lg = 12; };
+// Four-step split 2^lgN = 2^lgN1 * 2^lgN2 for lgN > kSmallMaxLg: rows of stage 2 at most 2^12
+// long, and at least 16 columns per stage-1/3 tile so every column segment spans >= 128 bytes.
+__host__ __device__ constexpr int split_lgN1(int lgN) {
+    return (lgN - kTileLg) > ((lgN / 2) < (kTileLg - 4) ? (lgN / 2) : (kTileLg - 4))
+               ? (lgN - kTileLg)
+               : ((lgN / 2) < (kTileLg - 4) ? (lgN / 2) : (kTileLg - 4));
+}
+
+// Lattices sharing one Bluestein length, launched together with kernels specialised for it.
+struct FftGroup {
+    int lgN;
+    int small;        // one-block path (lgN <= kSmallMaxLg)
+    int nlat;
+    const int* lat;   // device [nlat] lattice indices
+};
 
 // ---- launchers (defined in the .hip files) ---------------------------------------------------------
 struct FreqView {
@@ -107,13 +122,6 @@ struct TxArgs {
     int32_t* res32;           // device residues [max_nlat][n] (slot = lattice index within its transform)
     const HistTile* hist;     // device [nhist]
     int nhist;
-    // four-step tiling (large lattices)
-    const int* large;         // device [nlarge] lattice indices
-    const int* tile0_col;     // device [nlarge + 1] column-tile prefix sums
-    const int* tile0_row;     // device [nlarge + 1] row-tile prefix sums
-    int nlarge, tiles_col, tiles_row;
-    const int* small;         // device [nsmall] lattice indices
-    int nsmall;
     bool fast_mod;            // residues may use the fp64 quotient estimate
 };
 
@@ -131,26 +139,26 @@ template <typename T>
 void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval, hipStream_t s);
 void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s);
 
-// Bluestein stages.  sign = -1: DFT with e^{-2 pi i jm/M} (forward), +1: with e^{+...} (adjoint).
-// Stage "in": chirped input from src (samples, or the bins already in the work area) into work.
+// Bluestein stages for one group of lattices.  sign = -1: DFT with e^{-2 pi i jm/M} (forward),
+// +1: with e^{+...} (adjoint).  src: samples, or the bins already in the work area.
 template <typename T>
-void launch_bluestein_small(const TxArgs& a, const cx<T>* src, int64_t src_stride, bool src_is_samples,
-                            cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
+void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride,
+                            bool src_is_samples, cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
                             bool dst_is_samples, int sign, bool scale_by_invM, hipStream_t s);
 template <typename T>
-void launch_p1(const TxArgs& a, const cx<T>* src, int64_t src_stride, bool src_is_samples, cx<T>* work,
-               int sign, hipStream_t s);
+void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride, bool src_is_samples,
+               cx<T>* work, int sign, hipStream_t s);
 template <typename T>
-void launch_p2(const TxArgs& a, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s);
+void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s);
 template <typename T>
-void launch_p3(const TxArgs& a, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
+void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
                int sign, bool scale_by_invM, hipStream_t s);
 
 // Filter spectra: filt_l = DFT_{2^lgN}(b_l) / 2^lgN with b_l[n] = e^{+i pi n^2 / M_l} for |n| < M_l
 // (wrapped), stored in the layout stage 2 reads (natural order on the one-block path,
 // [k1][k2] = B[k1 + N1 k2] on the four-step path).
 template <typename T>
-void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cx<T>* filt, int64_t filt_total,
-                   int device, hipStream_t s);
+void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std::vector<FftGroup>& groups,
+                   cx<T>* filt, int device, hipStream_t s);
 
 }  // namespace mr1l

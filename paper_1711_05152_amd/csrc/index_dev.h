@@ -8,8 +8,17 @@ namespace mr1l {
 template <typename K>
 __device__ __forceinline__ int64_t dot_kz(const K* __restrict__ f, int64_t nf, int d, int64_t g,
                                           const int64_t* __restrict__ z) {
+    // components loaded in groups of 8 so that their loads are in flight together
     int64_t s = 0;
-    for (int c = 0; c < d; ++c) s += (int64_t)f[c * nf + g] * z[c];
+    int c = 0;
+    for (; c + 8 <= d; c += 8) {
+        int64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (int64_t)f[(c + u) * nf + g];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u] * z[c + u];
+    }
+    for (; c < d; ++c) s += (int64_t)f[c * nf + g] * z[c];
     return s;
 }
 

@@ -12,9 +12,12 @@
 //    stage 3 = inverse twiddles + inverse column DFTs + output chirp.  Stage 2 is where forward
 //    and inverse transforms meet, so the filter spectrum is stored in that stage's layout and the
 //    intermediate never needs a transpose.
-// All in-LDS DFTs are Stockham radix-8 (+ one radix-2/4 stage) with twiddles from a table.
+// All in-LDS DFTs are Stockham radix-8 (+ one radix-2/4 stage) with twiddles from a table, with
+// every length a compile-time constant: lattices are grouped by convolution length and each
+// group is launched with kernels specialised for its sizes.
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -155,49 +158,46 @@ template <typename T, int SIGN> struct Dft<T, 8, SIGN> {
     }
 };
 
-template <int R> struct Lg;
-template <> struct Lg<2> { static constexpr int v = 1; };
-template <> struct Lg<4> { static constexpr int v = 2; };
-template <> struct Lg<8> { static constexpr int v = 3; };
 
-// One Stockham radix-R stage over nseq sequences of length 2^lgN stored at buf[b*S + e].
-// Ns = 2^lgNs is the length of the sub-transforms already done.  Every thread holds E values.
-template <typename T, int E, int R, int SIGN>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, int lgN, int nseq, int S, int lgNs,
-                                          const cx<T>* __restrict__ tw) {
-    constexpr int NB = E / R;
-    constexpr int LR = Lg<R>::v;
-    const int lgNb = lgN - LR;
-    const int nbf = 1 << lgNb;
-    const int total = nbf * nseq;
+// ---- Stockham stages with compile-time sizes -------------------------------------------------------
+// NSEQ sequences of length 2^LGN stored at buf[pidx(b*S + e)].  2^LGNS is the length of the
+// sub-transforms already done; this stage has radix 2^LR.
+template <typename T, int LGN, int NSEQ, int S, int SIGN, int LGNS, int LR>
+__device__ __forceinline__ void stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw) {
+    constexpr int R = 1 << LR;
+    constexpr int LGNB = LGN - LR;
+    constexpr int NBF = 1 << LGNB;            // butterflies per sequence
+    constexpr int TOTAL = NBF * NSEQ;
+    constexpr int NB = (TOTAL + kThreads - 1) / kThreads;
+    constexpr bool FULL = (TOTAL % kThreads) == 0;
     cx<T> v[NB][R];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int g = threadIdx.x + u * kThreads;
-        if (g < total) {
-            const int b = g >> lgNb, j = g & (nbf - 1);
+        if (FULL || g < TOTAL) {
+            const int b = g >> LGNB, j = g & (NBF - 1);
             const int base = b * S + j;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(base + (r << lgNb))];
+            for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(base + (r << LGNB))];
         }
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int g = threadIdx.x + u * kThreads;
-        if (g < total) {
-            const int b = g >> lgNb, j = g & (nbf - 1);
-            const int k = j & ((1 << lgNs) - 1);
-            if (lgNs > 0) {
-                const int step = k << (kTwLg - lgNs - LR);   // w_{Ns R}^{k} = tw[k 4096/(Ns R)]
-                // powers w^r from table values w, w^2, w^4 (exact entries) and at most two products
+        if (FULL || g < TOTAL) {
+            const int b = g >> LGNB, j = g & (NBF - 1);
+            const int k = j & ((1 << LGNS) - 1);
+            if constexpr (LGNS > 0) {
+                const int step = k << (kTwLg - LGNS - LR);   // w_{Ns R}^{k} = tw[k 4096/(Ns R)]
+                // powers w^r from the exact table values w, w^2, w^4 and at most two products
                 cx<T> w[R];
                 w[1] = tw[step];
-                if (R >= 4) {
+                if constexpr (R >= 4) {
                     w[2] = tw[2 * step];
                     w[3] = cmul(w[1], w[2]);
                 }
-                if (R >= 8) {
+                if constexpr (R >= 8) {
                     w[4] = tw[4 * step];
                     w[5] = cmul(w[1], w[4]);
                     w[6] = cmul(w[2], w[4]);
@@ -209,165 +209,317 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int lgN, int nseq, int S, 
             Dft<T, R, SIGN>::run(v[u]);
             const int base = b * S + ((j - k) << LR) + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[pidx(base + (r << lgNs))] = v[u][r];
+            for (int r = 0; r < R; ++r) buf[pidx(base + (r << LGNS))] = v[u][r];
         }
     }
     __syncthreads();
 }
 
-// In-LDS DFT (SIGN -1: e^{-2 pi i nk/N}, +1: e^{+...}, unnormalized) of nseq sequences.
-// Requires nseq * 2^lgN <= kThreads * E.  Output in natural order.
-template <typename T, int E, int SIGN>
-__device__ __forceinline__ void lds_fft(cx<T>* buf, int lgN, int nseq, int S, const cx<T>* __restrict__ tw) {
-    int lgNs = 0;
-    const int rem = lgN % 3;
-    if (rem == 1) {
-        fft_stage<T, E, 2, SIGN>(buf, lgN, nseq, S, 0, tw);
-        lgNs = 1;
-    } else if (rem == 2) {
-        fft_stage<T, E, 4, SIGN>(buf, lgN, nseq, S, 0, tw);
-        lgNs = 2;
-    }
-    while (lgNs < lgN) {
-        fft_stage<T, E, 8, SIGN>(buf, lgN, nseq, S, lgNs, tw);
-        lgNs += 3;
+// In-LDS DFT (SIGN -1: e^{-2 pi i nk/N}, +1: e^{+...}, unnormalized), natural order in and out.
+template <typename T, int LGN, int NSEQ, int S, int SIGN, int LGNS = 0>
+__device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw) {
+    if constexpr (LGNS < LGN) {
+        constexpr int LR = (LGNS == 0 && (LGN % 3) != 0) ? (LGN % 3) : 3;
+        stage_ct<T, LGN, NSEQ, S, SIGN, LGNS, LR>(buf, tw);
+        fft_ct<T, LGN, NSEQ, S, SIGN, LGNS + LR>(buf, tw);
     }
 }
 
-__device__ __forceinline__ int find_seg(const int* __restrict__ pre, int n, int b) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= b) lo = mid; else hi = mid - 1;
+// ---- register-resident FFTs for the four-step tiles ------------------------------------------------
+// A tile holds NSEQ sequences of 2^LGN values (NSEQ * 2^LGN = 4096): every thread owns 16 values
+// of each stage.  The first stage takes its inputs from registers (the caller loads them from
+// global memory in that stage's order) and the last stage leaves its outputs in registers (the
+// caller stores them), so only the exchanges between stages go through LDS.  Radix 8 everywhere
+// except one radix-2/4 stage, placed first (REMF) or last.
+constexpr int n_stages(int lgn) { return lgn / 3 + ((lgn % 3) ? 1 : 0); }
+constexpr int stage_lr(int lgn, int i, bool remf) {
+    return (lgn % 3) == 0 ? 3 : (remf ? (i == 0 ? lgn % 3 : 3) : (i == n_stages(lgn) - 1 ? lgn % 3 : 3));
+}
+constexpr int stage_lgns(int lgn, int i, bool remf) {
+    int s = 0;
+    for (int k = 0; k < i; ++k) s += stage_lr(lgn, k, remf);
+    return s;
+}
+constexpr int kVals = (1 << kTileLg) / kThreads;   // values per thread (16)
+
+// butterfly u of this thread in a stage with 2^LGNB butterflies per sequence: (sequence b, index j).
+// BF: sequence index fastest across threads (column tiles), else j fastest (row tiles).
+template <int LGNB, int NSEQ, bool BF>
+__device__ __forceinline__ void bfly(int u, int& b, int& j) {
+    const int g = threadIdx.x + u * kThreads;
+    if constexpr (BF) {
+        b = g & (NSEQ - 1);
+        j = g / NSEQ;
+    } else {
+        b = g >> LGNB;
+        j = g & ((1 << LGNB) - 1);
     }
-    return lo;
+}
+
+// twiddles and radix-2^LR DFTs of stage I on the registers
+template <typename T, int LGN, int NSEQ, int SIGN, bool REMF, int I, bool BF>
+__device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict__ tw) {
+    constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
+    constexpr int LGNS = stage_lgns(LGN, I, REMF);
+    constexpr int LGNB = LGN - LR;
+    constexpr int NB = kVals / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        int b, j;
+        bfly<LGNB, NSEQ, BF>(u, b, j);
+        cx<T>* x = v + u * R;
+        if constexpr (LGNS > 0) {
+            const int k = j & ((1 << LGNS) - 1);
+            const int step = k << (kTwLg - LGNS - LR);
+            cx<T> w[R];
+            w[1] = tw[step];
+            if constexpr (R >= 4) {
+                w[2] = tw[2 * step];
+                w[3] = cmul(w[1], w[2]);
+            }
+            if constexpr (R >= 8) {
+                w[4] = tw[4 * step];
+                w[5] = cmul(w[1], w[4]);
+                w[6] = cmul(w[2], w[4]);
+                w[7] = cmul(w[3], w[4]);
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = SIGN < 0 ? cmul(x[r], w[r]) : cmulc(x[r], w[r]);
+        }
+        Dft<T, R, SIGN>::run(x);
+    }
+}
+
+// outputs of stage I -> LDS
+template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF>
+__device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
+    constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
+    constexpr int LGNS = stage_lgns(LGN, I, REMF);
+    constexpr int LGNB = LGN - LR;
+    constexpr int NB = kVals / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        int b, j;
+        bfly<LGNB, NSEQ, BF>(u, b, j);
+        const int k = j & ((1 << LGNS) - 1);
+        const int base = b * S + ((j - k) << LR) + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[pidx(base + (r << LGNS))] = v[u * R + r];
+    }
+}
+
+// inputs of stage I <- LDS
+template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF>
+__device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
+    constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
+    constexpr int LGNB = LGN - LR;
+    constexpr int NB = kVals / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        int b, j;
+        bfly<LGNB, NSEQ, BF>(u, b, j);
+        const int base = b * S + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u * R + r] = buf[pidx(base + (r << LGNB))];
+    }
+}
+
+// stages I..last; stage I's inputs are in v (mapping BF0 for I = 0, else j-fast); the last stage
+// uses mapping BFL.  On return v holds the last stage's outputs and all LDS reads are done.
+template <typename T, int LGN, int NSEQ, int S, int SIGN, bool REMF, bool BF0, bool BFL, int I = 0>
+__device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __restrict__ tw) {
+    constexpr int NS = n_stages(LGN);
+    constexpr bool BFI = (I == NS - 1) ? BFL : (I == 0 ? BF0 : false);
+    stage_compute<T, LGN, NSEQ, SIGN, REMF, I, BFI>(v, tw);
+    if constexpr (I + 1 < NS) {
+        constexpr bool BFN = (I + 1 == NS - 1) ? BFL : false;
+        stage_store<T, LGN, NSEQ, S, REMF, I, BFI>(buf, v);
+        __syncthreads();
+        stage_load<T, LGN, NSEQ, S, REMF, I + 1, BFN>(buf, v);
+        __syncthreads();
+        fft_regs<T, LGN, NSEQ, S, SIGN, REMF, BF0, BFL, I + 1>(buf, v, tw);
+    }
 }
 
 // ---- four-step stage 1 -----------------------------------------------------------------------------
+// One tile = C = 2^(12 - LGN1) columns of the N1 x N2 arrangement; tiles per lattice 2^(LGN - 12).
 // SRC 0: x = samples * chirp, 1: x = work (bins) * chirp, 2: x = work as is (all N entries).
-template <typename T, int SRC>
-__global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const cx<T>* __restrict__ src, int64_t src_stride,
-                                                 cx<T>* work, int sign, const cx<T>* __restrict__ tw) {
-    constexpr int LGE = TileElems<T>::lg;
-    constexpr int E = (1 << LGE) / kThreads;
-    __shared__ cx<T> lds[Padded<(1 << LGE) + 256>::v];
-    const int i = find_seg(a.tile0_col, a.nlarge + 1, blockIdx.x);
-    const LatDesc D = a.desc[a.large[i]];
-    const int lgN1 = D.lgN1, lgN2 = D.lgN2;
-    const int lgC = min(lgN2, LGE - lgN1);
-    const int C = 1 << lgC, N1 = 1 << lgN1;
-    const int c0 = (blockIdx.x - a.tile0_col[i]) << lgC;
-    const int S = N1 + 1;
+template <typename T, int LGN, int SRC>
+__global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict__ lat, const cx<T>* __restrict__ src,
+                                                 int64_t src_stride, cx<T>* work, int sign,
+                                                 const cx<T>* __restrict__ tw) {
+    constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
+    constexpr int LGC = kTileLg - LGN1, C = 1 << LGC, N1 = 1 << LGN1;
+    constexpr int S = N1 + 1;
+    constexpr int TPL_LG = LGN - kTileLg;
+    constexpr int NS = n_stages(LGN1);
+    constexpr int LR0 = stage_lr(LGN1, 0, true), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
+    constexpr int LRL = stage_lr(LGN1, NS - 1, true), RL = 1 << LRL, LGNBL = LGN1 - LRL;
+    __shared__ cx<T> lds[Padded<(1 << kTileLg) + C>::v];
+    const int li = blockIdx.x >> TPL_LG;
+    const int c0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGC;
+    const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     const cx<T>* in = src + rhs * src_stride + (SRC == 0 ? D.samp_off : D.work_off);
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
-    const int64_t nvalid = (SRC == 2) ? ((int64_t)1 << D.lgN) : D.M;
-    const int total = N1 << lgC;
-    for (int e = threadIdx.x; e < total; e += kThreads) {
-        const int col = e & (C - 1), n1 = e >> lgC;
-        const int64_t n = ((int64_t)n1 << lgN2) + c0 + col;
-        cx<T> v = {(T)0, (T)0};
-        if (n < nvalid) {
-            v = in[n];
-            if (SRC != 2) v = cmul(v, chirp<T>(n, D.M, D.invM, sign));
+    const int64_t nvalid = (SRC == 2) ? ((int64_t)1 << LGN) : D.M;
+    cx<T> v[kVals];
+#pragma unroll
+    for (int u = 0; u < kVals / R0; ++u) {
+        int col, j;
+        bfly<LGNB0, C, true>(u, col, j);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int64_t n = ((int64_t)(j + (r << LGNB0)) << LGN2) + c0 + col;
+            cx<T> x = {(T)0, (T)0};
+            if (n < nvalid) {
+                x = in[n];
+                if (SRC != 2) x = cmul(x, chirp<T>(n, D.M, D.invM, sign));
+            }
+            v[u * R0 + r] = x;
         }
-        lds[pidx(col * S + n1)] = v;
     }
-    __syncthreads();
-    lds_fft<T, E, -1>(lds, lgN1, C, S, tw);
-    {
-        // this thread's column n2 is fixed and k1 advances by kThreads/C: w_N^{n2 k1} by recurrence
-        const int col = threadIdx.x & (C - 1), n2 = c0 + col;
-        const int dk = kThreads >> lgC;
-        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * (threadIdx.x >> lgC)), D.lgN);
-        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 * dk) & ((1 << D.lgN) - 1)), D.lgN);
-        for (int e = threadIdx.x; e < total; e += kThreads) {
-            const int k1 = e >> lgC;
-            w[((int64_t)k1 << lgN2) + n2] = cmul(lds[pidx(col * S + k1)], wk);
+    fft_regs<T, LGN1, C, S, -1, true, true, true>(lds, v, tw);
+    // outputs: column col, k1 = j + r N1/RL; times w_N^{n2 k1}, stored at k1 N2 + n2
+#pragma unroll
+    for (int u = 0; u < kVals / RL; ++u) {
+        int col, j;
+        bfly<LGNBL, C, true>(u, col, j);
+        const int n2 = c0 + col;
+        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN);
+        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNBL) & ((1 << LGN) - 1)), LGN);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int k1 = j + (r << LGNBL);
+            w[((int64_t)k1 << LGN2) + n2] = cmul(v[u * RL + r], wk);
             wk = cmul(wk, ws);
         }
     }
 }
 
 // ---- four-step stage 2 -----------------------------------------------------------------------------
-// CONV: row DFT, multiply by the filter (conjugated for sign +1), inverse row DFT; else row DFT only.
-template <typename T, bool CONV>
-__global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, cx<T>* work, const cx<T>* __restrict__ filt, int sign,
+// One tile = 2^(12 - LGN2) rows.  CONV: row DFT, multiply by the filter (conjugated for sign +1),
+// inverse row DFT (the forward's last stage and the inverse's first stage are both radix 8 over
+// the same elements, so the product never leaves the registers); else row DFT only.
+template <typename T, int LGN, bool CONV>
+__global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
+                                                 const cx<T>* __restrict__ filt, int sign,
                                                  const cx<T>* __restrict__ tw) {
-    constexpr int LGE = TileElems<T>::lg;
-    constexpr int E = (1 << LGE) / kThreads;
-    __shared__ cx<T> lds[Padded<(1 << LGE)>::v];
-    const int i = find_seg(a.tile0_row, a.nlarge + 1, blockIdx.x);
-    const LatDesc D = a.desc[a.large[i]];
-    const int lgN1 = D.lgN1, lgN2 = D.lgN2;
-    const int lgR = min(lgN1, LGE - lgN2);
-    const int r0 = (blockIdx.x - a.tile0_row[i]) << lgR;
+    constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
+    constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2;
+    constexpr int TPL_LG = LGN - kTileLg;
+    constexpr int LR0 = stage_lr(LGN2, 0, true), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
+    constexpr int LGNB8 = LGN2 - 3;            // forward last / inverse first stage: radix 8
+    constexpr int NSI = n_stages(LGN2);
+    constexpr int LRL = stage_lr(LGN2, NSI - 1, false), RL = 1 << LRL, LGNBL = LGN2 - LRL;
+    static_assert(stage_lr(LGN2, n_stages(LGN2) - 1, true) == 3 && stage_lr(LGN2, 0, false) == 3, "radix 8 meet");
+    __shared__ cx<T> lds[Padded<(1 << kTileLg)>::v];
+    const int li = blockIdx.x >> TPL_LG;
+    const int r0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGR;
+    const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
-    cx<T>* w = work + rhs * a.work_stride + D.work_off + ((int64_t)r0 << lgN2);
-    const int total = 1 << (lgR + lgN2);
-    for (int e = threadIdx.x; e < total; e += kThreads) lds[pidx(e)] = w[e];
-    __syncthreads();
-    lds_fft<T, E, -1>(lds, lgN2, 1 << lgR, 1 << lgN2, tw);
-    if (CONV) {
-        const cx<T>* f = filt + D.filt_off + ((int64_t)r0 << lgN2);
-        for (int e = threadIdx.x; e < total; e += kThreads)
-            lds[pidx(e)] = sign < 0 ? cmul(lds[pidx(e)], f[e]) : cmulc(lds[pidx(e)], f[e]);
-        __syncthreads();
-        lds_fft<T, E, +1>(lds, lgN2, 1 << lgR, 1 << lgN2, tw);
+    cx<T>* w = work + rhs * a.work_stride + D.work_off + ((int64_t)r0 << LGN2);
+    cx<T> v[kVals];
+#pragma unroll
+    for (int u = 0; u < kVals / R0; ++u) {
+        int b, j;
+        bfly<LGNB0, ROWS, false>(u, b, j);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[u * R0 + r] = w[(b << LGN2) + j + (r << LGNB0)];
     }
-    for (int e = threadIdx.x; e < total; e += kThreads) w[e] = lds[pidx(e)];
+    fft_regs<T, LGN2, ROWS, N2, -1, true, false, false>(lds, v, tw);
+    if constexpr (CONV) {
+        const cx<T>* f = filt + D.filt_off + ((int64_t)r0 << LGN2);
+#pragma unroll
+        for (int u = 0; u < kVals / 8; ++u) {
+            int b, j;
+            bfly<LGNB8, ROWS, false>(u, b, j);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const cx<T> fv = f[(b << LGN2) + j + (r << LGNB8)];
+                v[u * 8 + r] = sign < 0 ? cmul(v[u * 8 + r], fv) : cmulc(v[u * 8 + r], fv);
+            }
+        }
+        fft_regs<T, LGN2, ROWS, N2, +1, false, false, false>(lds, v, tw);
+#pragma unroll
+        for (int u = 0; u < kVals / RL; ++u) {
+            int b, j;
+            bfly<LGNBL, ROWS, false>(u, b, j);
+#pragma unroll
+            for (int r = 0; r < RL; ++r) w[(b << LGN2) + j + (r << LGNBL)] = v[u * RL + r];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kVals / 8; ++u) {
+            int b, j;
+            bfly<LGNB8, ROWS, false>(u, b, j);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) w[(b << LGN2) + j + (r << LGNB8)] = v[u * 8 + r];
+        }
+    }
 }
 
 // ---- four-step stage 3 -----------------------------------------------------------------------------
-template <typename T, bool TO_SAMPLES>
-__global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, cx<T>* work, cx<T>* dst, int64_t dst_stride, int sign,
-                                                 int scale_by_invM, const cx<T>* __restrict__ tw) {
-    constexpr int LGE = TileElems<T>::lg;
-    constexpr int E = (1 << LGE) / kThreads;
-    __shared__ cx<T> lds[Padded<(1 << LGE) + 256>::v];
-    const int i = find_seg(a.tile0_col, a.nlarge + 1, blockIdx.x);
-    const LatDesc D = a.desc[a.large[i]];
-    const int lgN1 = D.lgN1, lgN2 = D.lgN2;
-    const int lgC = min(lgN2, LGE - lgN1);
-    const int C = 1 << lgC, N1 = 1 << lgN1;
-    const int c0 = (blockIdx.x - a.tile0_col[i]) << lgC;
-    const int S = N1 + 1;
+template <typename T, int LGN, bool TO_SAMPLES>
+__global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work, cx<T>* dst,
+                                                 int64_t dst_stride, int sign, int scale_by_invM,
+                                                 const cx<T>* __restrict__ tw) {
+    constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
+    constexpr int LGC = kTileLg - LGN1, C = 1 << LGC, N1 = 1 << LGN1;
+    constexpr int S = N1 + 1;
+    constexpr int TPL_LG = LGN - kTileLg;
+    constexpr int NS = n_stages(LGN1);
+    constexpr int LR0 = stage_lr(LGN1, 0, false), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
+    constexpr int LRL = stage_lr(LGN1, NS - 1, false), RL = 1 << LRL, LGNBL = LGN1 - LRL;
+    __shared__ cx<T> lds[Padded<(1 << kTileLg) + C>::v];
+    const int li = blockIdx.x >> TPL_LG;
+    const int c0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGC;
+    const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
-    const int total = N1 << lgC;
-    {
-        const int col = threadIdx.x & (C - 1), n2 = c0 + col;
-        const int dk = kThreads >> lgC;
-        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * (threadIdx.x >> lgC)), D.lgN);
-        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 * dk) & ((1 << D.lgN) - 1)), D.lgN);
-        for (int e = threadIdx.x; e < total; e += kThreads) {
-            const int k1 = e >> lgC;
-            lds[pidx(col * S + k1)] = cmulc(w[((int64_t)k1 << lgN2) + n2], wk);
+    cx<T> v[kVals];
+#pragma unroll
+    for (int u = 0; u < kVals / R0; ++u) {
+        int col, j;
+        bfly<LGNB0, C, true>(u, col, j);
+        const int n2 = c0 + col;
+        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN);
+        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNB0) & ((1 << LGN) - 1)), LGN);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k1 = j + (r << LGNB0);
+            v[u * R0 + r] = cmulc(w[((int64_t)k1 << LGN2) + n2], wk);
             wk = cmul(wk, ws);
         }
     }
-    __syncthreads();
-    lds_fft<T, E, +1>(lds, lgN1, C, S, tw);
+    fft_regs<T, LGN1, C, S, +1, false, true, true>(lds, v, tw);
     cx<T>* out = TO_SAMPLES ? dst + rhs * dst_stride + D.samp_off : w;
     const T sc = scale_by_invM ? (T)D.invM : (T)1;
-    for (int e = threadIdx.x; e < total; e += kThreads) {
-        const int col = e & (C - 1), n1 = e >> lgC;
-        const int64_t n = ((int64_t)n1 << lgN2) + c0 + col;
-        if (n < D.M) out[n] = cscale(cmul(lds[pidx(col * S + n1)], chirp<T>(n, D.M, D.invM, sign)), sc);
+    // the inverse column DFTs read all of the tile before any thread writes (fft_regs ends with a
+    // barrier after its last LDS read), so writing the outputs in place is safe
+#pragma unroll
+    for (int u = 0; u < kVals / RL; ++u) {
+        int col, j;
+        bfly<LGNBL, C, true>(u, col, j);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int n1 = j + (r << LGNBL);
+            const int64_t n = ((int64_t)n1 << LGN2) + c0 + col;
+            if (n < D.M) out[n] = cscale(cmul(v[u * RL + r], chirp<T>(n, D.M, D.invM, sign)), sc);
+        }
     }
 }
 
 // ---- one-block Bluestein ---------------------------------------------------------------------------
-template <typename T, bool SRC_SAMPLES, bool TO_SAMPLES>
-__global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const cx<T>* __restrict__ src, int64_t src_stride,
-                                                    cx<T>* work, const cx<T>* __restrict__ filt, cx<T>* dst,
-                                                    int64_t dst_stride, int sign, int scale_by_invM,
-                                                    const cx<T>* __restrict__ tw) {
-    constexpr int E = (1 << kSmallMaxLg) / kThreads;
-    __shared__ cx<T> lds[Padded<(1 << kSmallMaxLg)>::v];
-    const LatDesc D = a.desc[a.small[blockIdx.x]];
+template <typename T, int LGN, bool SRC_SAMPLES, bool TO_SAMPLES>
+__global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const int* __restrict__ lat,
+                                                    const cx<T>* __restrict__ src, int64_t src_stride, cx<T>* work,
+                                                    const cx<T>* __restrict__ filt, cx<T>* dst, int64_t dst_stride,
+                                                    int sign, int scale_by_invM, const cx<T>* __restrict__ tw) {
+    constexpr int N = 1 << LGN;
+    __shared__ cx<T> lds[Padded<N>::v];
+    const LatDesc D = a.desc[lat[blockIdx.x]];
     const int64_t rhs = blockIdx.y;
-    const int N = 1 << D.lgN;
     const cx<T>* in = src + rhs * src_stride + (SRC_SAMPLES ? D.samp_off : D.work_off);
     for (int n = threadIdx.x; n < N; n += kThreads) {
         cx<T> v = {(T)0, (T)0};
@@ -375,28 +527,29 @@ __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const cx<T>* __res
         lds[pidx(n)] = v;
     }
     __syncthreads();
-    lds_fft<T, E, -1>(lds, D.lgN, 1, N, tw);
+    fft_ct<T, LGN, 1, N, -1>(lds, tw);
     const cx<T>* f = filt + D.filt_off;
-    for (int n = threadIdx.x; n < N; n += kThreads) lds[pidx(n)] = sign < 0 ? cmul(lds[pidx(n)], f[n]) : cmulc(lds[pidx(n)], f[n]);
+    for (int n = threadIdx.x; n < N; n += kThreads)
+        lds[pidx(n)] = sign < 0 ? cmul(lds[pidx(n)], f[n]) : cmulc(lds[pidx(n)], f[n]);
     __syncthreads();
-    lds_fft<T, E, +1>(lds, D.lgN, 1, N, tw);
+    fft_ct<T, LGN, 1, N, +1>(lds, tw);
     cx<T>* out = TO_SAMPLES ? dst + rhs * dst_stride + D.samp_off : work + rhs * a.work_stride + D.work_off;
     const T sc = scale_by_invM ? (T)D.invM : (T)1;
     for (int n = threadIdx.x; n < D.M; n += kThreads)
         out[n] = cscale(cmul(lds[pidx(n)], chirp<T>(n, D.M, D.invM, sign)), sc);
 }
 
-// plain in-place forward DFT of the whole region (filter construction, one-block lattices)
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_small_dft(TxArgs a, cx<T>* work, const cx<T>* __restrict__ tw) {
-    constexpr int E = (1 << kSmallMaxLg) / kThreads;
-    __shared__ cx<T> lds[Padded<(1 << kSmallMaxLg)>::v];
-    const LatDesc D = a.desc[a.small[blockIdx.x]];
-    const int N = 1 << D.lgN;
-    cx<T>* w = work + D.work_off;
+// plain in-place forward DFT of a whole region (filter construction on the one-block path)
+template <int LGN>
+__global__ __launch_bounds__(kThreads) void k_small_dft(TxArgs a, const int* __restrict__ lat, cx<double>* work,
+                                                        const cx<double>* __restrict__ tw) {
+    constexpr int N = 1 << LGN;
+    __shared__ cx<double> lds[Padded<N>::v];
+    const LatDesc D = a.desc[lat[blockIdx.x]];
+    cx<double>* w = work + D.work_off;
     for (int n = threadIdx.x; n < N; n += kThreads) lds[pidx(n)] = w[n];
     __syncthreads();
-    lds_fft<T, E, -1>(lds, D.lgN, 1, N, tw);
+    fft_ct<double, LGN, 1, N, -1>(lds, tw);
     for (int n = threadIdx.x; n < N; n += kThreads) w[n] = lds[pidx(n)];
 }
 
@@ -410,9 +563,7 @@ __global__ void k_filter_fill(const LatDesc* __restrict__ desc, int L, cx<double
         if (n < D.M) m = n;
         else if (N - n < D.M) m = N - n;
         cx<double> v = {0.0, 0.0};
-        if (m >= 0) {
-            v = cispi<double>(sq_mod_2M(m, D.M, 0.5 * D.invM) * D.invM);
-        }
+        if (m >= 0) v = cispi<double>(sq_mod_2M(m, D.M, 0.5 * D.invM) * D.invM);
         tmp[D.work_off + n] = v;
     }
 }
@@ -429,157 +580,143 @@ __global__ void k_filter_store(const LatDesc* __restrict__ desc, const cx<double
     }
 }
 
-// ---- launchers -------------------------------------------------------------------------------------
-template <typename T>
-void launch_bluestein_small(const TxArgs& a, const cx<T>* src, int64_t src_stride, bool src_is_samples,
-                            cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
-                            int sign, bool scale_by_invM, hipStream_t s) {
-    if (a.nsmall == 0 || a.n_rhs == 0) return;
-    int dev = 0;
-    hipGetDevice(&dev);
-    const cx<T>* tw = twiddles<T>(dev);
-    dim3 grid(a.nsmall, (unsigned)a.n_rhs);
-    if (src_is_samples && !dst_is_samples)
-        hipLaunchKernelGGL((k_small<T, true, false>), grid, dim3(kThreads), 0, s, a, src, src_stride, work, filt, dst,
-                           dst_stride, sign, (int)scale_by_invM, tw);
-    else if (!src_is_samples && dst_is_samples)
-        hipLaunchKernelGGL((k_small<T, false, true>), grid, dim3(kThreads), 0, s, a, src, src_stride, work, filt, dst,
-                           dst_stride, sign, (int)scale_by_invM, tw);
-    else if (src_is_samples && dst_is_samples)
-        hipLaunchKernelGGL((k_small<T, true, true>), grid, dim3(kThreads), 0, s, a, src, src_stride, work, filt, dst,
-                           dst_stride, sign, (int)scale_by_invM, tw);
-    else
-        hipLaunchKernelGGL((k_small<T, false, false>), grid, dim3(kThreads), 0, s, a, src, src_stride, work, filt,
-                           dst, dst_stride, sign, (int)scale_by_invM, tw);
+// ---- dispatch over compile-time sizes --------------------------------------------------------------
+// f(std::integral_constant<int, lg>) for lg in [LO, HI]
+template <int LO, int HI, typename F>
+static void with_lg(int lg, F&& f) {
+    if constexpr (LO <= HI) {
+        if (lg == LO) f(std::integral_constant<int, LO>{});
+        else with_lg<LO + 1, HI>(lg, f);
+    }
 }
 
 template <typename T>
-void launch_p1(const TxArgs& a, const cx<T>* src, int64_t src_stride, bool src_is_samples, cx<T>* work, int sign,
-               hipStream_t s) {
-    if (a.nlarge == 0 || a.n_rhs == 0) return;
+void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride,
+                            bool src_is_samples, cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
+                            bool dst_is_samples, int sign, bool scale_by_invM, hipStream_t s) {
+    if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    dim3 grid(a.tiles_col, (unsigned)a.n_rhs);
-    if (src_is_samples)
-        hipLaunchKernelGGL((k_p1<T, 0>), grid, dim3(kThreads), 0, s, a, src, src_stride, work, sign, tw);
-    else
-        hipLaunchKernelGGL((k_p1<T, 1>), grid, dim3(kThreads), 0, s, a, src, src_stride, work, sign, tw);
+    const dim3 grid(g.nlat, (unsigned)a.n_rhs);
+    with_lg<0, kSmallMaxLg>(g.lgN, [&](auto LG) {
+        constexpr int lg = decltype(LG)::value;
+        if (src_is_samples && !dst_is_samples)
+            hipLaunchKernelGGL((k_small<T, lg, true, false>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride,
+                               work, filt, dst, dst_stride, sign, (int)scale_by_invM, tw);
+        else
+            hipLaunchKernelGGL((k_small<T, lg, false, true>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride,
+                               work, filt, dst, dst_stride, sign, (int)scale_by_invM, tw);
+    });
 }
 
 template <typename T>
-void launch_p2(const TxArgs& a, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s) {
-    if (a.nlarge == 0 || a.n_rhs == 0) return;
+void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride, bool src_is_samples,
+               cx<T>* work, int sign, hipStream_t s) {
+    if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    dim3 grid(a.tiles_row, (unsigned)a.n_rhs);
-    hipLaunchKernelGGL((k_p2<T, true>), grid, dim3(kThreads), 0, s, a, work, filt, sign, tw);
+    const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
+    with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
+        constexpr int lg = decltype(LG)::value;
+        if (src_is_samples)
+            hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
+        else
+            hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
+    });
 }
 
 template <typename T>
-void launch_p3(const TxArgs& a, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples, int sign,
-               bool scale_by_invM, hipStream_t s) {
-    if (a.nlarge == 0 || a.n_rhs == 0) return;
+void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s) {
+    if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    dim3 grid(a.tiles_col, (unsigned)a.n_rhs);
-    if (dst_is_samples)
-        hipLaunchKernelGGL((k_p3<T, true>), grid, dim3(kThreads), 0, s, a, work, dst, dst_stride, sign,
-                           (int)scale_by_invM, tw);
-    else
-        hipLaunchKernelGGL((k_p3<T, false>), grid, dim3(kThreads), 0, s, a, work, dst, dst_stride, sign,
-                           (int)scale_by_invM, tw);
+    const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
+    with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
+        constexpr int lg = decltype(LG)::value;
+        hipLaunchKernelGGL((k_p2<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, filt, sign, tw);
+    });
+}
+
+template <typename T>
+void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
+               int sign, bool scale_by_invM, hipStream_t s) {
+    if (g.nlat == 0 || a.n_rhs == 0) return;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const cx<T>* tw = twiddles<T>(dev);
+    const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
+    with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
+        constexpr int lg = decltype(LG)::value;
+        if (dst_is_samples)
+            hipLaunchKernelGGL((k_p3<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, dst, dst_stride, sign,
+                               (int)scale_by_invM, tw);
+        else
+            hipLaunchKernelGGL((k_p3<T, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, work, dst, dst_stride,
+                               sign, (int)scale_by_invM, tw);
+    });
 }
 
 #define MR1L_INST_FFT(T)                                                                                           \
-    template void launch_bluestein_small<T>(const TxArgs&, const cx<T>*, int64_t, bool, cx<T>*, const cx<T>*,      \
-                                            cx<T>*, int64_t, bool, int, bool, hipStream_t);                      \
-    template void launch_p1<T>(const TxArgs&, const cx<T>*, int64_t, bool, cx<T>*, int, hipStream_t);             \
-    template void launch_p2<T>(const TxArgs&, cx<T>*, const cx<T>*, int, hipStream_t);                            \
-    template void launch_p3<T>(const TxArgs&, cx<T>*, cx<T>*, int64_t, bool, int, bool, hipStream_t);
+    template void launch_bluestein_small<T>(const TxArgs&, const FftGroup&, const cx<T>*, int64_t, bool, cx<T>*,   \
+                                            const cx<T>*, cx<T>*, int64_t, bool, int, bool, hipStream_t);        \
+    template void launch_p1<T>(const TxArgs&, const FftGroup&, const cx<T>*, int64_t, bool, cx<T>*, int,          \
+                               hipStream_t);                                                                      \
+    template void launch_p2<T>(const TxArgs&, const FftGroup&, cx<T>*, const cx<T>*, int, hipStream_t);           \
+    template void launch_p3<T>(const TxArgs&, const FftGroup&, cx<T>*, cx<T>*, int64_t, bool, int, bool,          \
+                               hipStream_t);
 MR1L_INST_FFT(float)
 MR1L_INST_FFT(double)
 
 // Filter spectra for every lattice of a plan (synchronous on s).  The double-precision DFT of
-// b_l reuses the four-step stages 1-2 (or the one-block DFT) on a temporary buffer laid out like
-// the work area (work_off, length 2^lgN).
+// b_l reuses the stage-1/stage-2 kernels (or the one-block DFT) on a temporary buffer laid out
+// like the work area; the four-step split is the one the plan's own stage 2 reads.
 template <typename T>
-void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cx<T>* filt, int64_t filt_total,
-                   int device, hipStream_t s) {
+void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std::vector<FftGroup>& groups,
+                   cx<T>* filt, int device, hipStream_t s) {
     if (L == 0) return;
-    (void)filt_total;
     int64_t tot = 0;
     int maxlg = 0;
-    std::vector<int> smalls, larges, t0c, t0r;
-    int tc = 0, tr = 0;
     for (int l = 0; l < L; ++l) {
         tot = std::max<int64_t>(tot, hdesc[l].work_off + ((int64_t)1 << hdesc[l].lgN));
         maxlg = std::max(maxlg, hdesc[l].lgN);
-        if (hdesc[l].small) {
-            smalls.push_back(l);
-        } else {
-            larges.push_back(l);
-            constexpr int LGE = TileElems<double>::lg;
-            const int lgC = std::min(hdesc[l].lgN2, LGE - hdesc[l].lgN1);
-            const int lgR = std::min(hdesc[l].lgN1, LGE - hdesc[l].lgN2);
-            t0c.push_back(tc);
-            t0r.push_back(tr);
-            tc += 1 << (hdesc[l].lgN2 - lgC);
-            tr += 1 << (hdesc[l].lgN1 - lgR);
-        }
     }
-    t0c.push_back(tc);
-    t0r.push_back(tr);
     cx<double>* tmp = nullptr;
-    int* dsm = nullptr;
-    int* dlg = nullptr;
-    int* dt0c = nullptr;
-    int* dt0r = nullptr;
-    hipMalloc(&tmp, tot * sizeof(cx<double>));
-    hipMalloc(&dsm, (smalls.size() + 1) * sizeof(int));
-    hipMalloc(&dlg, (larges.size() + 1) * sizeof(int));
-    hipMalloc(&dt0c, t0c.size() * sizeof(int));
-    hipMalloc(&dt0r, t0r.size() * sizeof(int));
-    if (!smalls.empty()) hipMemcpy(dsm, smalls.data(), smalls.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (!larges.empty()) hipMemcpy(dlg, larges.data(), larges.size() * sizeof(int), hipMemcpyHostToDevice);
-    hipMemcpy(dt0c, t0c.data(), t0c.size() * sizeof(int), hipMemcpyHostToDevice);
-    hipMemcpy(dt0r, t0r.data(), t0r.size() * sizeof(int), hipMemcpyHostToDevice);
-
+    (void)hipMalloc(&tmp, tot * sizeof(cx<double>));
     TxArgs a{};
     a.desc = ddesc;
     a.L = L;
     a.n_rhs = 1;
     a.work_stride = 0;
-    a.large = dlg;
-    a.tile0_col = dt0c;
-    a.tile0_row = dt0r;
-    a.nlarge = (int)larges.size();
-    a.tiles_col = tc;
-    a.tiles_row = tr;
-    a.small = dsm;
-    a.nsmall = (int)smalls.size();
     const cx<double>* tw = twiddles<double>(device);
-
     const int blocks = std::max(1, std::min(1024, (int)(((int64_t)1 << maxlg) / 256)));
     hipLaunchKernelGGL(k_filter_fill, dim3(blocks, L), dim3(256), 0, s, ddesc, L, tmp);
-    if (a.nsmall) hipLaunchKernelGGL(k_small_dft<double>, dim3(a.nsmall), dim3(kThreads), 0, s, a, tmp, tw);
-    if (a.nlarge) {
-        hipLaunchKernelGGL((k_p1<double, 2>), dim3(tc, 1), dim3(kThreads), 0, s, a, (const cx<double>*)tmp,
-                           (int64_t)0, tmp, -1, tw);
-        hipLaunchKernelGGL((k_p2<double, false>), dim3(tr, 1), dim3(kThreads), 0, s, a, tmp,
-                           (const cx<double>*)nullptr, -1, tw);
+    for (const FftGroup& g : groups) {
+        if (g.small) {
+            with_lg<0, kSmallMaxLg>(g.lgN, [&](auto LG) {
+                hipLaunchKernelGGL((k_small_dft<decltype(LG)::value>), dim3(g.nlat), dim3(kThreads), 0, s, a, g.lat,
+                                   tmp, tw);
+            });
+        } else {
+            const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), 1);
+            with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
+                constexpr int lg = decltype(LG)::value;
+                hipLaunchKernelGGL((k_p1<double, lg, 2>), grid, dim3(kThreads), 0, s, a, g.lat,
+                                   (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw);
+                hipLaunchKernelGGL((k_p2<double, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, tmp,
+                                   (const cx<double>*)nullptr, -1, tw);
+            });
+        }
     }
     hipLaunchKernelGGL((k_filter_store<T>), dim3(blocks, L), dim3(256), 0, s, ddesc, (const cx<double>*)tmp, filt);
-    hipStreamSynchronize(s);
-    hipFree(tmp);
-    hipFree(dsm);
-    hipFree(dlg);
-    hipFree(dt0c);
-    hipFree(dt0r);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tmp);
 }
-template void build_filters<float>(const LatDesc*, int, const LatDesc*, cx<float>*, int64_t, int, hipStream_t);
-template void build_filters<double>(const LatDesc*, int, const LatDesc*, cx<double>*, int64_t, int, hipStream_t);
+template void build_filters<float>(const LatDesc*, int, const LatDesc*, const std::vector<FftGroup>&, cx<float>*, int,
+                                   hipStream_t);
+template void build_filters<double>(const LatDesc*, int, const LatDesc*, const std::vector<FftGroup>&, cx<double>*,
+                                    int, hipStream_t);
 
 }  // namespace mr1l

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -31,8 +32,6 @@ static int ceil_lg(int64_t v) {
     return lg;
 }
 
-template <typename T>
-static int tile_lg() { return TileElems<T>::lg; }
 
 static mr1l_status check_distinct_rows(const int32_t* f, int64_t n, int d) {
     std::vector<int64_t> idx(n);
@@ -137,9 +136,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     P->hdesc.resize(L);
     P->samp_off.assign(L + 1, 0);
     int64_t woff = 0, bmoff = 0;
-    std::vector<int> smalls, larges, t0c, t0r;
-    int tc = 0, tr = 0;
-    const int LGE = tile_lg<T>();
+    std::map<int, std::vector<int>> by_len;   // Bluestein length -> lattices
     for (int l = 0; l < L; ++l) {
         LatDesc& D = P->hdesc[l];
         D.M = sp.M[l];
@@ -148,7 +145,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->samp_off[l + 1] = P->samp_off[l] + D.M;
         D.lgN = ceil_lg(2 * D.M - 1);
         D.small = D.lgN <= kSmallMaxLg;
-        D.lgN1 = D.small ? 0 : D.lgN / 2;
+        D.lgN1 = D.small ? 0 : split_lgN1(D.lgN);
         D.lgN2 = D.lgN - D.lgN1;
         D.work_off = woff;
         D.filt_off = woff;
@@ -157,20 +154,8 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         D.bm_off = bmoff;
         bmoff += 2 * D.bm_words;
         D.zoff = (int64_t)l * d;
-        if (D.small) {
-            smalls.push_back(l);
-        } else {
-            larges.push_back(l);
-            t0c.push_back(tc);
-            t0r.push_back(tr);
-            const int lgC = std::min(D.lgN2, LGE - D.lgN1);
-            const int lgR = std::min(D.lgN1, LGE - D.lgN2);
-            tc += 1 << (D.lgN2 - lgC);
-            tr += 1 << (D.lgN1 - lgR);
-        }
+        by_len[D.lgN].push_back(l);
     }
-    t0c.push_back(tc);
-    t0r.push_back(tr);
     P->sum_M = P->samp_off[L];
     P->work_stride = woff;
     P->filt_total = woff;
@@ -193,15 +178,28 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     MR1L_HIP_TRY(P->tx.upload(P->htx.data(), P->htx.size() * sizeof(TxDesc)));
     MR1L_HIP_TRY(P->tx_foff.upload(foff.data(), foff.size() * sizeof(int64_t)));
     MR1L_HIP_TRY(P->z.upload(zred.data(), zred.size() * sizeof(int64_t)));
-    MR1L_HIP_TRY(P->small.upload(smalls.data(), smalls.size() * sizeof(int)));
-    MR1L_HIP_TRY(P->large.upload(larges.data(), larges.size() * sizeof(int)));
-    MR1L_HIP_TRY(P->t0c.upload(t0c.data(), t0c.size() * sizeof(int)));
-    MR1L_HIP_TRY(P->t0r.upload(t0r.data(), t0r.size() * sizeof(int)));
+    {
+        std::vector<int> ids;
+        std::vector<std::pair<int, int>> spans;   // (lgN, first index)
+        for (auto& kv : by_len) {
+            spans.push_back({kv.first, (int)ids.size()});
+            ids.insert(ids.end(), kv.second.begin(), kv.second.end());
+        }
+        MR1L_HIP_TRY(P->grp_lat.upload(ids.data(), ids.size() * sizeof(int)));
+        for (size_t i = 0; i < spans.size(); ++i) {
+            FftGroup g;
+            g.lgN = spans[i].first;
+            g.small = g.lgN <= kSmallMaxLg;
+            g.nlat = (int)by_len[g.lgN].size();
+            g.lat = P->grp_lat.as<int>() + spans[i].second;
+            P->groups.push_back(g);
+        }
+    }
     // alias-histogram tiles: every lattice's bins split into ranges of <= 2^18 bins (multiples of
     // 32), several per lattice when there are few lattices so that enough workgroups run
     std::vector<HistTile> tiles;
     {
-        const int rpl = std::max(1, std::min(8, 256 / std::max(1, L)));
+        const int rpl = std::max(1, std::min(4, 128 / std::max(1, L)));
         int txi = 0;
         for (int l = 0; l < L; ++l) {
             while (txi + 1 < ntx && l >= P->htx[txi].lat0 + P->htx[txi].nlat) ++txi;
@@ -252,20 +250,12 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     a.res32 = P->res32.as<int32_t>();
     a.hist = P->hist.as<HistTile>();
     a.nhist = (int)tiles.size();
-    a.large = P->large.as<int>();
-    a.tile0_col = P->t0c.as<int>();
-    a.tile0_row = P->t0r.as<int>();
-    a.nlarge = (int)larges.size();
-    a.tiles_col = tc;
-    a.tiles_row = tr;
-    a.small = P->small.as<int>();
-    a.nsmall = (int)smalls.size();
 
     if (!twiddles<T>(sp.device) || !twiddles<double>(sp.device)) {
         set_error("could not allocate twiddle tables");
         return MR1L_ERR_NOMEM;
     }
-    if (!sh) build_filters<T>(P->hdesc.data(), L, a.desc, (cx<T>*)P->filt_ptr, P->filt_total, sp.device, nullptr);
+    if (!sh) build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, (cx<T>*)P->filt_ptr, sp.device, nullptr);
     MR1L_HIP_TRY(hipGetLastError());
     MR1L_HIP_TRY(hipDeviceSynchronize());
     *out = guard.release();
@@ -334,20 +324,22 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
         a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
         const cx<T>* yc = y + r0 * a.samp_stride;
         cx<T>* cc = c + r0 * a.n;
-        if (a.nsmall) {
-            tm.begin(1);
-            launch_bluestein_small<T>(a, yc, a.samp_stride, true, work, filt, work, a.work_stride, false, -1, !eval, s);
-            tm.end();
-        }
-        if (a.nlarge) {
+        for (const FftGroup& g : p->groups) {
+            if (g.small) {
+                tm.begin(1);
+                launch_bluestein_small<T>(a, g, yc, a.samp_stride, true, work, filt, work, a.work_stride, false, -1,
+                                          !eval, s);
+                tm.end();
+                continue;
+            }
             tm.begin(2);
-            launch_p1<T>(a, yc, a.samp_stride, true, work, -1, s);
+            launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, s);
             tm.end();
             tm.begin(3);
-            launch_p2<T>(a, work, filt, -1, s);
+            launch_p2<T>(a, g, work, filt, -1, s);
             tm.end();
             tm.begin(4);
-            launch_p3<T>(a, work, work, a.work_stride, false, -1, !eval, s);
+            launch_p3<T>(a, g, work, work, a.work_stride, false, -1, !eval, s);
             tm.end();
         }
         tm.begin(5);
@@ -376,20 +368,22 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
         launch_clear_bins<T>(a, work, s);
         launch_scatter<T>(a, cc, work, eval, s);
         tm.end();
-        if (a.nsmall) {
-            tm.begin(1);
-            launch_bluestein_small<T>(a, work, a.work_stride, false, work, filt, yc, a.samp_stride, true, +1, !eval, s);
-            tm.end();
-        }
-        if (a.nlarge) {
+        for (const FftGroup& g : p->groups) {
+            if (g.small) {
+                tm.begin(1);
+                launch_bluestein_small<T>(a, g, work, a.work_stride, false, work, filt, yc, a.samp_stride, true, +1,
+                                          !eval, s);
+                tm.end();
+                continue;
+            }
             tm.begin(2);
-            launch_p1<T>(a, work, a.work_stride, false, work, +1, s);
+            launch_p1<T>(a, g, work, a.work_stride, false, work, +1, s);
             tm.end();
             tm.begin(3);
-            launch_p2<T>(a, work, filt, +1, s);
+            launch_p2<T>(a, g, work, filt, +1, s);
             tm.end();
             tm.begin(4);
-            launch_p3<T>(a, work, yc, a.samp_stride, true, +1, !eval, s);
+            launch_p3<T>(a, g, work, yc, a.samp_stride, true, +1, !eval, s);
             tm.end();
         }
     }

@@ -136,7 +136,8 @@ struct Plan {
     int64_t work_stride = 0;
     int64_t filt_total = 0;
     int64_t bm_total = 0;
-    DevMem freqs, desc, tx, tx_foff, z, bitmaps, filt, work, large, small, t0c, t0r, res32, hist;
+    DevMem freqs, desc, tx, tx_foff, z, bitmaps, filt, work, grp_lat, res32, hist;
+    std::vector<FftGroup> groups;   // lattices grouped by Bluestein length
     void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};
     // per-stage timing
