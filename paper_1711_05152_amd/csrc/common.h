@@ -47,6 +47,8 @@ struct LatDesc {
     int32_t lgN1;      // four-step split: 2^lgN = 2^lgN1 * 2^lgN2 (lgN1 = 0 on the one-block path)
     int32_t lgN2;
     int32_t small;     // 1: the whole Bluestein convolution runs in one workgroup
+    int32_t rt0;       // fused residue/histogram pass: first ResTile of this lattice
+    int32_t rtn;       //   and their number
 };
 
 // One entry per independent transform of a plan (a plain plan has one; a batched plan many).
@@ -68,6 +70,15 @@ struct HistTile {
     int32_t m1;
 };
 constexpr int kHistMaxBins = 1 << 18;   // 2 x 2^18 bits = 64 KiB of LDS bitmaps per workgroup
+
+// One workgroup of the fused residue + alias-histogram pass: frequencies [k0, k1) of transform tx
+// against lattice l, counted into LDS bitmaps over all M_l bins; the workgroup's partial bitmaps
+// (seen then multi, bm_words each) go to word offset part of the partial-bitmap area.
+struct ResTile {
+    int64_t k0, k1, part;
+    int32_t l, tx;
+};
+constexpr int kFusedMaxWords = 1 << 14;   // bitmaps of up to 2^19 bins (2 x 64 KiB of LDS)
 
 // Frequencies are kept component-major (structure of arrays) in the narrowest signed integer
 // type that holds them.
@@ -120,9 +131,22 @@ struct TxArgs {
     uint32_t* bitmaps;        // device alias bitmaps
     int64_t bm_total;         // words of all bitmaps
     int32_t* res32;           // device residues [max_nlat][n] (slot = lattice index within its transform)
-    const HistTile* hist;     // device [nhist]
+    const HistTile* hist;     // device [nhist] (l = -1: idle slot of the XCD-interleaved order)
     int nhist;
+    int hist_words;           // largest bitmap words of one tile (LDS per bitmap)
+    // fused residue + histogram pass (every lattice has at most kFusedMaxWords bitmap words)
+    bool fused;
+    const ResTile* rtiles;    // device [nrt]
+    int nrt;
+    int rt_words;             // largest bm_words over the lattices (LDS per bitmap)
+    uint32_t* part;           // partial bitmaps of every ResTile
     bool fast_mod;            // residues may use the fp64 quotient estimate
+    // 32-bit residue path: |k . z| < 2^31 for every frequency and lattice, |k_c| < 2^23 and d <= 32;
+    // z32 holds the reduced generators as int32 rows padded with zeros
+    bool narrow;
+    int zpad;                 // 8, 12, 16, 24 or 32: components the residue kernels multiply
+    int zrow;                 // row stride of z32 (16 or 32)
+    const int32_t* z32;
 };
 
 template <typename T> const cx<T>* twiddles(int device);   // e^{-2 pi i m/4096}, m < 4096
@@ -134,7 +158,7 @@ void launch_alias(const TxArgs& a, bool histogram, hipStream_t s);
 template <typename T>
 void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval, hipStream_t s);
 template <typename T>
-void launch_clear_bins(const TxArgs& a, cx<T>* work, hipStream_t s);
+void launch_clear_bins(const TxArgs& a, cx<T>* work, hipStream_t s);   // Fourier-matrix adjoint only
 template <typename T>
 void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval, hipStream_t s);
 void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s);
@@ -144,10 +168,12 @@ void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* 
 template <typename T>
 void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride,
                             bool src_is_samples, cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
-                            bool dst_is_samples, int sign, bool scale_by_invM, hipStream_t s);
+                            bool dst_is_samples, int sign, bool scale_by_invM, bool mask_bins, hipStream_t s);
+// mask_bins: the bins in the work area are valid only where the alias bitmaps mark them as holding
+// exactly one frequency (adjoint of Alg. 2); the others are read as zero
 template <typename T>
 void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride, bool src_is_samples,
-               cx<T>* work, int sign, hipStream_t s);
+               cx<T>* work, int sign, bool mask_bins, hipStream_t s);
 template <typename T>
 void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s);
 template <typename T>

@@ -107,6 +107,12 @@ __device__ __forceinline__ cx<T> chirp(int64_t n, int64_t M, double invM, int si
     return cispi<T>((double)sign * (sq_mod_2M(n, M, 0.5 * invM) * invM));
 }
 
+// bin m of lattice D holds exactly one frequency: seen and not multi in the alias bitmaps
+__device__ __forceinline__ bool owned_bin(const uint32_t* __restrict__ bm, const LatDesc& D, int64_t m) {
+    const uint32_t s = bm[D.bm_off + (m >> 5)], x = bm[D.bm_off + D.bm_words + (m >> 5)];
+    return ((s & ~x) >> (m & 31)) & 1u;
+}
+
 // LDS index with one pad slot after every 8 elements: strided Stockham writes and column loads
 // then spread over the banks instead of piling onto a few.
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
@@ -343,7 +349,9 @@ __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __re
 
 // ---- four-step stage 1 -----------------------------------------------------------------------------
 // One tile = C = 2^(12 - LGN1) columns of the N1 x N2 arrangement; tiles per lattice 2^(LGN - 12).
-// SRC 0: x = samples * chirp, 1: x = work (bins) * chirp, 2: x = work as is (all N entries).
+// SRC 0: x = samples * chirp, 1: x = work (bins) * chirp, 2: x = work as is (all N entries),
+// 3: x = work (bins) * chirp where the alias bitmaps mark the bin as holding exactly one frequency,
+// else 0 (the adjoint's scatter writes only those bins).
 template <typename T, int LGN, int SRC>
 __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict__ lat, const cx<T>* __restrict__ src,
                                                  int64_t src_stride, cx<T>* work, int sign,
@@ -375,6 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
             if (n < nvalid) {
                 x = in[n];
                 if (SRC != 2) x = cmul(x, chirp<T>(n, D.M, D.invM, sign));
+                if (SRC == 3 && !owned_bin(a.bitmaps, D, n)) x = {(T)0, (T)0};
             }
             v[u * R0 + r] = x;
         }
@@ -515,7 +524,8 @@ template <typename T, int LGN, bool SRC_SAMPLES, bool TO_SAMPLES>
 __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const int* __restrict__ lat,
                                                     const cx<T>* __restrict__ src, int64_t src_stride, cx<T>* work,
                                                     const cx<T>* __restrict__ filt, cx<T>* dst, int64_t dst_stride,
-                                                    int sign, int scale_by_invM, const cx<T>* __restrict__ tw) {
+                                                    int sign, int scale_by_invM, int mask_bins,
+                                                    const cx<T>* __restrict__ tw) {
     constexpr int N = 1 << LGN;
     __shared__ cx<T> lds[Padded<N>::v];
     const LatDesc D = a.desc[lat[blockIdx.x]];
@@ -524,6 +534,7 @@ __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const int* __restr
     for (int n = threadIdx.x; n < N; n += kThreads) {
         cx<T> v = {(T)0, (T)0};
         if (n < D.M) v = cmul(in[n], chirp<T>(n, D.M, D.invM, sign));
+        if (!SRC_SAMPLES && mask_bins && n < D.M && !owned_bin(a.bitmaps, D, n)) v = {(T)0, (T)0};
         lds[pidx(n)] = v;
     }
     __syncthreads();
@@ -593,7 +604,7 @@ static void with_lg(int lg, F&& f) {
 template <typename T>
 void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride,
                             bool src_is_samples, cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
-                            bool dst_is_samples, int sign, bool scale_by_invM, hipStream_t s) {
+                            bool dst_is_samples, int sign, bool scale_by_invM, bool mask_bins, hipStream_t s) {
     if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -603,16 +614,16 @@ void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src
         constexpr int lg = decltype(LG)::value;
         if (src_is_samples && !dst_is_samples)
             hipLaunchKernelGGL((k_small<T, lg, true, false>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride,
-                               work, filt, dst, dst_stride, sign, (int)scale_by_invM, tw);
+                               work, filt, dst, dst_stride, sign, (int)scale_by_invM, 0, tw);
         else
             hipLaunchKernelGGL((k_small<T, lg, false, true>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride,
-                               work, filt, dst, dst_stride, sign, (int)scale_by_invM, tw);
+                               work, filt, dst, dst_stride, sign, (int)scale_by_invM, (int)mask_bins, tw);
     });
 }
 
 template <typename T>
 void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride, bool src_is_samples,
-               cx<T>* work, int sign, hipStream_t s) {
+               cx<T>* work, int sign, bool mask_bins, hipStream_t s) {
     if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -622,6 +633,8 @@ void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src
         constexpr int lg = decltype(LG)::value;
         if (src_is_samples)
             hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
+        else if (mask_bins)
+            hipLaunchKernelGGL((k_p1<T, lg, 3>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
         else
             hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
     });
@@ -661,8 +674,8 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
 
 #define MR1L_INST_FFT(T)                                                                                           \
     template void launch_bluestein_small<T>(const TxArgs&, const FftGroup&, const cx<T>*, int64_t, bool, cx<T>*,   \
-                                            const cx<T>*, cx<T>*, int64_t, bool, int, bool, hipStream_t);        \
-    template void launch_p1<T>(const TxArgs&, const FftGroup&, const cx<T>*, int64_t, bool, cx<T>*, int,          \
+                                            const cx<T>*, cx<T>*, int64_t, bool, int, bool, bool, hipStream_t);  \
+    template void launch_p1<T>(const TxArgs&, const FftGroup&, const cx<T>*, int64_t, bool, cx<T>*, int, bool,    \
                                hipStream_t);                                                                      \
     template void launch_p2<T>(const TxArgs&, const FftGroup&, cx<T>*, const cx<T>*, int, hipStream_t);           \
     template void launch_p3<T>(const TxArgs&, const FftGroup&, cx<T>*, cx<T>*, int64_t, bool, int, bool,          \

@@ -13,6 +13,9 @@
 #include "common.h"
 #include "index_dev.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace mr1l {
 
 __global__ void k_clear_u32(uint32_t* p, int64_t words) {
@@ -38,13 +41,157 @@ __global__ __launch_bounds__(256) void k_residues(TxArgs a) {
     }
 }
 
-constexpr int kHistThreads = 1024;
+// 32-bit path: one thread per frequency, its d components loaded once into registers and every
+// lattice of its transform done in turn.  Products of 24-bit operands wrap modulo 2^32, which is
+// exact because the plan checked |k . z| < 2^31; the quotient estimate in double is off by at
+// most one and the remainder s - qM is exact in double.
+template <typename K, int DP, bool SINGLE>
+__global__ __launch_bounds__(256) void k_residues_narrow(TxArgs a) {
+    const K* __restrict__ f = (const K*)a.fv.f;
+    const int dl = a.fv.d - 1;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        int kv[DP];
+#pragma unroll
+        for (int c = 0; c < DP; ++c) kv[c] = (int)f[(int64_t)min(c, dl) * a.fv.nf + g];
+        for (int j = 0; j < t.nlat; ++j) {
+            const int l = t.lat0 + j;
+            const int32_t* __restrict__ zz = a.z32 + (int64_t)l * a.zrow;
+            int s = 0;
+#pragma unroll
+            for (int c = 0; c < DP; ++c) s = __mul24(kv[c], zz[c]) + s;
+            const int M = (int)a.desc[l].M;
+            const double q = floor((double)s * a.desc[l].invM);
+            int r = (int)fma(-q, (double)M, (double)s);
+            r += r < 0 ? M : 0;
+            r -= r >= M ? M : 0;
+            a.res32[(int64_t)j * a.n + g] = r;
+        }
+    }
+}
+
+// r = k . z mod M on the 32-bit path; zr is z_l padded with zeros to DP entries, so components
+// past d (loaded from the clamped address of the last one) contribute nothing and every load is
+// unconditional (all of them in flight together).  g < 2^31 (plan-checked), so the component
+// loads take a uniform base and a 32-bit offset.
+template <typename K, int DP>
+__device__ __forceinline__ int residue_narrow(const TxArgs& a, const int* zr, int M, double invM, uint32_t g) {
+    const K* __restrict__ f = (const K*)a.fv.f;
+    const int dl = a.fv.d - 1;
+    int kv[DP];
+#pragma unroll
+    for (int c = 0; c < DP; ++c) kv[c] = (int)(f + (int64_t)min(c, dl) * a.fv.nf)[g];
+    int s = 0;
+#pragma unroll
+    for (int c = 0; c < DP; ++c) s = __mul24(kv[c], zr[c]) + s;
+    const double q = floor((double)s * invM);
+    int r = (int)fma(-q, (double)M, (double)s);
+    r += r < 0 ? M : 0;
+    r -= r >= M ? M : 0;
+    return r;
+}
+
+// Fused residues + alias histogram (Alg. 2, definition of I_l): one workgroup per ResTile computes
+// r_l(k) for its chunk of frequencies, stores them, and counts them into LDS bitmaps covering all
+// bins of lattice l (2-bit saturating counts: seen, multi); the partial bitmaps are written out
+// whole and combined by k_hist_merge.
+constexpr int kResThreads = 512;
+constexpr int kResUnroll = 4;
+
+template <typename K, int DP>
+__global__ __launch_bounds__(kResThreads) void k_res_hist(TxArgs a) {
+    extern __shared__ uint32_t rh_lds[];
+    const ResTile rt = a.rtiles[blockIdx.x];
+    const LatDesc D = a.desc[rt.l];
+    const TxDesc t = a.tx[rt.tx];
+    const int j = rt.l - t.lat0;
+    const int words = (int)D.bm_words;
+    uint32_t* seen = rh_lds;
+    uint32_t* multi = rh_lds + a.rt_words;
+    for (int w = threadIdx.x; w < words; w += kResThreads) {
+        seen[w] = 0u;
+        multi[w] = 0u;
+    }
+    __syncthreads();
+    int32_t* res = a.res32 + (int64_t)j * a.n;
+    const int64_t last = rt.k1 - 1;
+    constexpr int DZ = DP > 0 ? DP : 1;
+    int zr[DZ];
+#pragma unroll
+    for (int c = 0; c < DZ; ++c) zr[c] = DP > 0 ? a.z32[(int64_t)rt.l * a.zrow + c] : 0;
+    const int M = (int)D.M;
+    for (int64_t kb = rt.k0 + threadIdx.x; kb < rt.k1; kb += kResThreads * kResUnroll) {
+        int r[kResUnroll];
+#pragma unroll
+        for (int u = 0; u < kResUnroll; ++u) {
+            const int64_t g = min(kb + (int64_t)u * kResThreads, last);   // clamped: loads stay in range
+            if (DP > 0) r[u] = residue_narrow<K, DZ>(a, zr, M, D.invM, (uint32_t)g);
+            else r[u] = (int)residue<K>(a, D, g);
+        }
+        uint32_t old[kResUnroll];
+#pragma unroll
+        for (int u = 0; u < kResUnroll; ++u) {
+            const int64_t g = kb + (int64_t)u * kResThreads;
+            old[u] = 0u;
+            if (g <= last) {
+                res[(uint32_t)g] = r[u];
+                old[u] = atomicOr(&seen[r[u] >> 5], 1u << (r[u] & 31));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kResUnroll; ++u)
+            if ((old[u] >> (r[u] & 31)) & 1u) atomicOr(&multi[r[u] >> 5], 1u << (r[u] & 31));
+    }
+    __syncthreads();
+    uint32_t* p = a.part + rt.part;
+    for (int w = threadIdx.x; w < words; w += kResThreads) {
+        p[w] = seen[w];
+        p[words + w] = multi[w];
+    }
+}
+
+// bitmaps of lattice blockIdx.y from its partial bitmaps (consecutive, 2 bm_words apart): multi =
+// some partial multi, or seen in two partials
+__global__ __launch_bounds__(256) void k_hist_merge(TxArgs a) {
+    const LatDesc D = a.desc[blockIdx.y];
+    const int64_t words = D.bm_words;
+    const uint32_t* p0 = a.part + a.rtiles[D.rt0].part;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t sa = 0u, ma = 0u;
+        int i = 0;
+        for (; i + 8 <= D.rtn; i += 8) {
+            uint32_t ps[8], pm[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ps[u] = p0[(int64_t)(i + u) * 2 * words + w];
+                pm[u] = p0[(int64_t)(i + u) * 2 * words + words + w];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ma |= pm[u] | (sa & ps[u]);
+                sa |= ps[u];
+            }
+        }
+        for (; i < D.rtn; ++i) {
+            const uint32_t ps = p0[(int64_t)i * 2 * words + w], pm = p0[(int64_t)i * 2 * words + words + w];
+            ma |= pm | (sa & ps);
+            sa |= ps;
+        }
+        a.bitmaps[D.bm_off + w] = sa;
+        a.bitmaps[D.bm_off + words + w] = ma;
+    }
+}
+
+constexpr int kHistThreads = 512;
 constexpr int kHistUnroll = 16;
 
+// LDS: seen[hist_words] then multi[hist_words] (dynamic)
 __global__ __launch_bounds__(kHistThreads) void k_hist_lds(TxArgs a) {
-    __shared__ uint32_t seen[kHistMaxBins / 32];
-    __shared__ uint32_t multi[kHistMaxBins / 32];
+    extern __shared__ uint32_t hist_lds[];
     const HistTile h = a.hist[blockIdx.x];
+    if (h.l < 0) return;
+    uint32_t* seen = hist_lds;
+    uint32_t* multi = hist_lds + a.hist_words;
     const LatDesc D = a.desc[h.l];
     const TxDesc t = a.tx[h.tx];
     const int words = (h.m1 - h.m0 + 31) >> 5;
@@ -79,73 +226,74 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(TxArgs a) {
     }
 }
 
-constexpr int kRB = 4;  // right-hand sides per thread in gather/scatter
-constexpr int kLC = 8;  // lattices whose loads are issued together
+constexpr int kRB = 4;  // right-hand sides per thread in gather/scatter with several right-hand sides
 
-// unaliased flags of lattices j0 .. j0+kLC-1 for frequency g; residues returned in r
-template <bool SINGLE>
+// unaliased flags of lattice slots j0 .. j0+LC-1 for frequency g (bit u set: k in I_l); residues in r.
+// All LC residue loads, then all LC bitmap loads, are issued together.
+template <int LC>
 __device__ __forceinline__ uint32_t unaliased_chunk(const TxArgs& a, const TxDesc& t, int j0, int64_t g,
                                                     int32_t* r) {
     const int jl = t.nlat - 1;
 #pragma unroll
-    for (int u = 0; u < kLC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, jl) * a.n + g];
-    uint32_t w[kLC];
+    for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, jl) * a.n + g];
+    uint32_t w[LC];
 #pragma unroll
-    for (int u = 0; u < kLC; ++u) {
+    for (int u = 0; u < LC; ++u) {
         const LatDesc& D = a.desc[t.lat0 + min(j0 + u, jl)];
         w[u] = a.bitmaps[D.bm_off + D.bm_words + (r[u] >> 5)];
     }
-#pragma unroll
-    for (int u = 0; u < kLC; ++u)
-        if (j0 + u > jl) w[u] = 0xffffffffu;
     uint32_t mask = 0;
 #pragma unroll
-    for (int u = 0; u < kLC; ++u) mask |= (((w[u] >> (r[u] & 31)) & 1u) ^ 1u) << u;
+    for (int u = 0; u < LC; ++u)
+        if (j0 + u <= jl) mask |= (((w[u] >> (r[u] & 31)) & 1u) ^ 1u) << u;
     return mask;
 }
 
-template <typename T, bool EVAL, bool SINGLE>
+// lattice slots handled per chunk: all 16 loads in flight for one right-hand side, 8 for kRB
+template <int RB> struct GatherChunk { static constexpr int v = RB == 1 ? 16 : 8; };
+
+template <typename T, bool EVAL, bool SINGLE, int RB>
 __global__ __launch_bounds__(256) void k_gather(TxArgs a, const cx<T>* __restrict__ work, cx<T>* coeffs) {
-    const int64_t rhs0 = (int64_t)blockIdx.y * kRB;
-    const int nr = (int)min((int64_t)kRB, a.n_rhs - rhs0);
+    constexpr int LC = GatherChunk<RB>::v;
+    const int64_t rhs0 = (int64_t)blockIdx.y * RB;
+    const int nr = (int)min((int64_t)RB, a.n_rhs - rhs0);
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
         const TxDesc t = get_tx<SINGLE>(a, g);
-        cx<T> acc[kRB];
+        cx<T> acc[RB];
 #pragma unroll
-        for (int q = 0; q < kRB; ++q) acc[q] = {(T)0, (T)0};
+        for (int q = 0; q < RB; ++q) acc[q] = {(T)0, (T)0};
         int cnt = 0;
-        for (int j0 = 0; j0 < t.nlat; j0 += kLC) {
-            int32_t r[kLC];
+        for (int j0 = 0; j0 < t.nlat; j0 += LC) {
+            int32_t r[LC];
             uint32_t use;
             if (EVAL) {
 #pragma unroll
-                for (int u = 0; u < kLC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, t.nlat - 1) * a.n + g];
-                use = (t.nlat - j0 >= kLC) ? 0xffu : ((1u << (t.nlat - j0)) - 1u);
+                for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, t.nlat - 1) * a.n + g];
+                use = (t.nlat - j0 >= LC) ? (uint32_t)((1ull << LC) - 1) : ((1u << (t.nlat - j0)) - 1u);
             } else {
-                use = unaliased_chunk<SINGLE>(a, t, j0, g, r);
-                if (t.nlat - j0 < kLC) use &= (1u << (t.nlat - j0)) - 1u;
+                use = unaliased_chunk<LC>(a, t, j0, g, r);
                 cnt += __popc(use);
             }
-            cx<T> v[kLC][kRB];
+            cx<T> v[LC][RB];
 #pragma unroll
-            for (int u = 0; u < kLC; ++u) {
+            for (int u = 0; u < LC; ++u) {
                 if ((use >> u) & 1u) {
                     const cx<T>* src = work + rhs0 * a.work_stride + a.desc[t.lat0 + j0 + u].work_off + r[u];
 #pragma unroll
-                    for (int q = 0; q < kRB; ++q)
+                    for (int q = 0; q < RB; ++q)
                         if (q < nr) v[u][q] = src[q * a.work_stride];
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kLC; ++u)   // ascending l
+            for (int u = 0; u < LC; ++u)   // ascending l
                 if ((use >> u) & 1u) {
 #pragma unroll
-                    for (int q = 0; q < kRB; ++q)
+                    for (int q = 0; q < RB; ++q)
                         if (q < nr) acc[q] = acc[q] + v[u][q];
                 }
         }
 #pragma unroll
-        for (int q = 0; q < kRB; ++q) {
+        for (int q = 0; q < RB; ++q) {
             if (q < nr) {
                 cx<T> v = acc[q];
                 if (!EVAL) v = cnt ? cx<T>{v.x / (T)cnt, v.y / (T)cnt} : cx<T>{(T)0, (T)0};
@@ -155,7 +303,8 @@ __global__ __launch_bounds__(256) void k_gather(TxArgs a, const cx<T>* __restric
     }
 }
 
-// zero the first M_l entries (the DFT bins) of every lattice's work region
+// zero the first M_l entries (the DFT bins) of every lattice's work region (Fourier-matrix
+// adjoint, which accumulates into the bins)
 template <typename T>
 __global__ void k_clear_bins(TxArgs a, cx<T>* work) {
     const int l = blockIdx.y;
@@ -166,49 +315,61 @@ __global__ void k_clear_bins(TxArgs a, cx<T>* work) {
         w[m] = {(T)0, (T)0};
 }
 
-template <typename T, bool EVAL, bool SINGLE>
-__global__ __launch_bounds__(256) void k_scatter(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
-    const int64_t rhs0 = (int64_t)blockIdx.y * kRB;
-    const int nr = (int)min((int64_t)kRB, a.n_rhs - rhs0);
+// Fourier-matrix adjoint: bins[r_l(k)] += c_k over every lattice
+template <typename T, bool SINGLE, int RB>
+__global__ __launch_bounds__(256) void k_scatter_eval(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
+    const int64_t rhs0 = (int64_t)blockIdx.y * RB;
+    const int nr = (int)min((int64_t)RB, a.n_rhs - rhs0);
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
         const TxDesc t = get_tx<SINGLE>(a, g);
-        cx<T> v[kRB];
+        cx<T> v[RB];
 #pragma unroll
-        for (int q = 0; q < kRB; ++q) v[q] = (q < nr) ? coeffs[(rhs0 + q) * a.n + g] : cx<T>{(T)0, (T)0};
-        if (EVAL) {
-            for (int j = 0; j < t.nlat; ++j) {
-                const int64_t r = a.res32[(int64_t)j * a.n + g];
-                cx<T>* dst = work + rhs0 * a.work_stride + a.desc[t.lat0 + j].work_off + r;
+        for (int q = 0; q < RB; ++q) v[q] = (q < nr) ? coeffs[(rhs0 + q) * a.n + g] : cx<T>{(T)0, (T)0};
+        for (int j = 0; j < t.nlat; ++j) {
+            const int64_t r = a.res32[(int64_t)j * a.n + g];
+            cx<T>* dst = work + rhs0 * a.work_stride + a.desc[t.lat0 + j].work_off + r;
 #pragma unroll
-                for (int q = 0; q < kRB; ++q)
-                    if (q < nr) {
-                        atomicAdd(&dst[q * a.work_stride].x, v[q].x);
-                        atomicAdd(&dst[q * a.work_stride].y, v[q].y);
-                    }
-            }
-            continue;
+            for (int q = 0; q < RB; ++q)
+                if (q < nr) {
+                    atomicAdd(&dst[q * a.work_stride].x, v[q].x);
+                    atomicAdd(&dst[q * a.work_stride].y, v[q].y);
+                }
         }
-        // counter_k over all lattices, keeping the first chunk's flags and residues
-        int cnt = 0;
-        for (int j0 = 0; j0 < t.nlat; j0 += kLC) {
-            int32_t r[kLC];
-            uint32_t use = unaliased_chunk<SINGLE>(a, t, j0, g, r);
-            if (t.nlat - j0 < kLC) use &= (1u << (t.nlat - j0)) - 1u;
-            cnt += __popc(use);
+    }
+}
+
+// Adjoint of Alg. 2: bins[r_l(k)] = c_k / counter_k for every lattice where k is unaliased.  Only
+// unaliased bins are written; the bins that stay stale (empty or shared) are masked out by stage 1
+// of the Bluestein transform through the same alias bitmaps, so no clearing pass is needed.
+template <typename T, bool SINGLE, int RB>
+__global__ __launch_bounds__(256) void k_scatter(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
+    constexpr int LC = GatherChunk<RB>::v;
+    const int64_t rhs0 = (int64_t)blockIdx.y * RB;
+    const int nr = (int)min((int64_t)RB, a.n_rhs - rhs0);
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        cx<T> v[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) v[q] = (q < nr) ? coeffs[(rhs0 + q) * a.n + g] : cx<T>{(T)0, (T)0};
+        if (t.nlat == 0) continue;
+        int32_t r[LC];
+        uint32_t use = unaliased_chunk<LC>(a, t, 0, g, r);
+        int cnt = __popc(use);
+        for (int j0 = LC; j0 < t.nlat; j0 += LC) {   // counter_k over the remaining lattices
+            int32_t rx[LC];
+            cnt += __popc(unaliased_chunk<LC>(a, t, j0, g, rx));
         }
         if (cnt == 0) continue;
 #pragma unroll
-        for (int q = 0; q < kRB; ++q) v[q] = {v[q].x / (T)cnt, v[q].y / (T)cnt};
-        for (int j0 = 0; j0 < t.nlat; j0 += kLC) {
-            int32_t r[kLC];
-            uint32_t use = unaliased_chunk<SINGLE>(a, t, j0, g, r);
-            if (t.nlat - j0 < kLC) use &= (1u << (t.nlat - j0)) - 1u;
+        for (int q = 0; q < RB; ++q) v[q] = {v[q].x / (T)cnt, v[q].y / (T)cnt};
+        for (int j0 = 0; j0 < t.nlat; j0 += LC) {
+            if (j0 > 0) use = unaliased_chunk<LC>(a, t, j0, g, r);
 #pragma unroll
-            for (int u = 0; u < kLC; ++u)
+            for (int u = 0; u < LC; ++u)
                 if ((use >> u) & 1u) {
                     cx<T>* dst = work + rhs0 * a.work_stride + a.desc[t.lat0 + j0 + u].work_off + r[u];
 #pragma unroll
-                    for (int q = 0; q < kRB; ++q)
+                    for (int q = 0; q < RB; ++q)
                         if (q < nr) dst[q * a.work_stride] = v[q];
                 }
         }
@@ -245,36 +406,78 @@ void launch_clear_u32(uint32_t* p, int64_t words, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_u32, dim3(grid_for(words)), dim3(256), 0, s, p, words);
 }
 
+template <int DP, typename K>
+static void launch_res_narrow(const TxArgs& a, hipStream_t s) {
+    const dim3 grid(grid_for(a.n, 256, 65535));
+    if (a.ntx == 1) hipLaunchKernelGGL((k_residues_narrow<K, DP, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_residues_narrow<K, DP, false>), grid, dim3(256), 0, s, a);
+}
+
+template <typename K>
+static void launch_res(const TxArgs& a, hipStream_t s) {
+    if (a.narrow) {
+        if (a.zrow == 16) launch_res_narrow<16, K>(a, s);
+        else launch_res_narrow<32, K>(a, s);
+        return;
+    }
+    const dim3 grid(grid_for(a.n, 256, 65535), (unsigned)a.max_nlat);
+    if (a.ntx == 1) hipLaunchKernelGGL((k_residues<K, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_residues<K, false>), grid, dim3(256), 0, s, a);
+}
+
+template <typename K, int DP>
+static void launch_res_hist_k(const TxArgs& a, hipStream_t s) {
+    const size_t lds = 2 * (size_t)a.rt_words * sizeof(uint32_t);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_res_hist<K, DP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_res_hist<K, DP>), dim3(a.nrt), dim3(kResThreads), lds, s, a);
+}
+
+template <typename K>
+static void launch_res_hist(const TxArgs& a, hipStream_t s) {
+    if (!a.narrow) launch_res_hist_k<K, 0>(a, s);
+    else if (a.zpad == 8) launch_res_hist_k<K, 8>(a, s);
+    else if (a.zpad == 12) launch_res_hist_k<K, 12>(a, s);
+    else if (a.zpad == 16) launch_res_hist_k<K, 16>(a, s);
+    else if (a.zpad == 24) launch_res_hist_k<K, 24>(a, s);
+    else launch_res_hist_k<K, 32>(a, s);
+}
+
 void launch_alias(const TxArgs& a, bool histogram, hipStream_t s) {
     if (a.n == 0 || a.L == 0) return;
-    const dim3 grid(grid_for(a.n, 256, 65535), (unsigned)a.max_nlat);
-    const bool single = a.ntx == 1;
-    switch (a.fv.ktype) {
-        case K_I8:
-            if (single) hipLaunchKernelGGL((k_residues<int8_t, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_residues<int8_t, false>), grid, dim3(256), 0, s, a);
-            break;
-        case K_I16:
-            if (single) hipLaunchKernelGGL((k_residues<int16_t, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_residues<int16_t, false>), grid, dim3(256), 0, s, a);
-            break;
-        default:
-            if (single) hipLaunchKernelGGL((k_residues<int32_t, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_residues<int32_t, false>), grid, dim3(256), 0, s, a);
-            break;
+    if (histogram && a.fused) {
+        switch (a.fv.ktype) {
+            case K_I8: launch_res_hist<int8_t>(a, s); break;
+            case K_I16: launch_res_hist<int16_t>(a, s); break;
+            default: launch_res_hist<int32_t>(a, s); break;
+        }
+        const unsigned gx = (unsigned)std::max(1, std::min(64, (a.rt_words + 255) / 256));
+        hipLaunchKernelGGL(k_hist_merge, dim3(gx, (unsigned)a.L), dim3(256), 0, s, a);
+        return;
     }
-    if (histogram) hipLaunchKernelGGL(k_hist_lds, dim3(a.nhist), dim3(kHistThreads), 0, s, a);
+    switch (a.fv.ktype) {
+        case K_I8: launch_res<int8_t>(a, s); break;
+        case K_I16: launch_res<int16_t>(a, s); break;
+        default: launch_res<int32_t>(a, s); break;
+    }
+    if (histogram)
+        hipLaunchKernelGGL(k_hist_lds, dim3(a.nhist), dim3(kHistThreads), 2 * a.hist_words * sizeof(uint32_t), s, a);
 }
 
 template <typename T>
 void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval, hipStream_t s) {
     if (a.n == 0 || a.n_rhs == 0) return;
-    const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + kRB - 1) / kRB));
     const bool single = a.ntx == 1;
-    if (eval && single) hipLaunchKernelGGL((k_gather<T, true, true>), grid, dim3(256), 0, s, a, work, coeffs);
-    else if (eval) hipLaunchKernelGGL((k_gather<T, true, false>), grid, dim3(256), 0, s, a, work, coeffs);
-    else if (single) hipLaunchKernelGGL((k_gather<T, false, true>), grid, dim3(256), 0, s, a, work, coeffs);
-    else hipLaunchKernelGGL((k_gather<T, false, false>), grid, dim3(256), 0, s, a, work, coeffs);
+    auto go = [&](auto RBc) {
+        constexpr int RB = decltype(RBc)::value;
+        const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
+        if (eval && single) hipLaunchKernelGGL((k_gather<T, true, true, RB>), grid, dim3(256), 0, s, a, work, coeffs);
+        else if (eval) hipLaunchKernelGGL((k_gather<T, true, false, RB>), grid, dim3(256), 0, s, a, work, coeffs);
+        else if (single) hipLaunchKernelGGL((k_gather<T, false, true, RB>), grid, dim3(256), 0, s, a, work, coeffs);
+        else hipLaunchKernelGGL((k_gather<T, false, false, RB>), grid, dim3(256), 0, s, a, work, coeffs);
+    };
+    if (a.n_rhs == 1) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, kRB>{});
 }
 
 template <typename T>
@@ -286,12 +489,17 @@ void launch_clear_bins(const TxArgs& a, cx<T>* work, hipStream_t s) {
 template <typename T>
 void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval, hipStream_t s) {
     if (a.n == 0 || a.n_rhs == 0) return;
-    const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + kRB - 1) / kRB));
     const bool single = a.ntx == 1;
-    if (eval && single) hipLaunchKernelGGL((k_scatter<T, true, true>), grid, dim3(256), 0, s, a, coeffs, work);
-    else if (eval) hipLaunchKernelGGL((k_scatter<T, true, false>), grid, dim3(256), 0, s, a, coeffs, work);
-    else if (single) hipLaunchKernelGGL((k_scatter<T, false, true>), grid, dim3(256), 0, s, a, coeffs, work);
-    else hipLaunchKernelGGL((k_scatter<T, false, false>), grid, dim3(256), 0, s, a, coeffs, work);
+    auto go = [&](auto RBc) {
+        constexpr int RB = decltype(RBc)::value;
+        const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
+        if (eval && single) hipLaunchKernelGGL((k_scatter_eval<T, true, RB>), grid, dim3(256), 0, s, a, coeffs, work);
+        else if (eval) hipLaunchKernelGGL((k_scatter_eval<T, false, RB>), grid, dim3(256), 0, s, a, coeffs, work);
+        else if (single) hipLaunchKernelGGL((k_scatter<T, true, RB>), grid, dim3(256), 0, s, a, coeffs, work);
+        else hipLaunchKernelGGL((k_scatter<T, false, RB>), grid, dim3(256), 0, s, a, coeffs, work);
+    };
+    if (a.n_rhs == 1) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, kRB>{});
 }
 
 void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s) {

@@ -132,6 +132,18 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         return MR1L_ERR_OVERFLOW;
     }
     P->args.fast_mod = bound < 0x1.0p52L;
+    P->args.narrow = d <= 32 && maxabs < ((int64_t)1 << 23) && bound < 0x1.0p31L && n < ((int64_t)1 << 31);
+    if (P->args.narrow) {
+        const int zp = d <= 8 ? 8 : d <= 12 ? 12 : d <= 16 ? 16 : d <= 24 ? 24 : 32;
+        const int zrow = zp <= 16 ? 16 : 32;   // row stride of the table, >= every kernel's width
+        std::vector<int32_t> z32((size_t)std::max(1, L) * zrow, 0);
+        for (int l = 0; l < L; ++l)
+            for (int c = 0; c < d; ++c) z32[(size_t)l * zrow + c] = (int32_t)zred[(size_t)l * d + c];
+        MR1L_HIP_TRY(P->z32.upload(z32.data(), z32.size() * sizeof(int32_t)));
+        P->args.zpad = zp;
+        P->args.zrow = zrow;
+        P->args.z32 = P->z32.as<int32_t>();
+    }
 
     P->hdesc.resize(L);
     P->samp_off.assign(L + 1, 0);
@@ -196,10 +208,15 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         }
     }
     // alias-histogram tiles: every lattice's bins split into ranges of <= 2^18 bins (multiples of
-    // 32), several per lattice when there are few lattices so that enough workgroups run
+    // 32), enough of them that a few hundred workgroups run.  Every tile streams all residues of its
+    // lattice, so with >= 8 lattices the tiles of lattice l are placed on workgroup slots
+    // b = l (mod 8): workgroups are dealt to the 8 XCDs round-robin, so each lattice's residues are
+    // then read into one XCD's L2 only (idle slots pad uneven groups).
     std::vector<HistTile> tiles;
+    int hist_words = 1;
     {
-        const int rpl = std::max(1, std::min(4, 128 / std::max(1, L)));
+        const int rpl = std::max(1, std::min(16, (512 + L - 1) / std::max(1, L)));
+        std::vector<std::vector<HistTile>> byx(L >= 8 ? 8 : 1);
         int txi = 0;
         for (int l = 0; l < L; ++l) {
             while (txi + 1 < ntx && l >= P->htx[txi].lat0 + P->htx[txi].nlat) ++txi;
@@ -207,11 +224,50 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             int64_t nr = std::max<int64_t>((M + kHistMaxBins - 1) / kHistMaxBins, rpl);
             nr = std::min<int64_t>(nr, (M + 31) / 32);
             int64_t step = ((M + nr - 1) / nr + 31) / 32 * 32;
+            hist_words = std::max<int>(hist_words, (int)(step / 32));
             for (int64_t m0 = 0; m0 < M; m0 += step)
-                tiles.push_back(HistTile{l, txi, (int32_t)m0, (int32_t)std::min(M, m0 + step)});
+                byx[l % byx.size()].push_back(HistTile{l, txi, (int32_t)m0, (int32_t)std::min(M, m0 + step)});
         }
+        size_t most = 0;
+        for (auto& v : byx) most = std::max(most, v.size());
+        for (size_t i = 0; i < most; ++i)
+            for (auto& v : byx) tiles.push_back(i < v.size() ? v[i] : HistTile{-1, 0, 0, 0});
     }
     MR1L_HIP_TRY(P->hist.upload(tiles.data(), tiles.size() * sizeof(HistTile)));
+    // fused residue + histogram tiles: each lattice's frequencies split into P_l chunks, each
+    // counted over all bins in LDS; P_l keeps the partial bitmaps (2 words per 32 bins per chunk)
+    // near half the residue bytes while giving chunks of >= 1024 frequencies
+    bool fused = L > 0 && n < ((int64_t)1 << 31);   // 32-bit frequency offsets inside the kernel
+    int rt_words = 1;
+    for (int l = 0; l < L; ++l) fused = fused && P->hdesc[l].bm_words <= kFusedMaxWords;
+    std::vector<ResTile> rtiles;
+    int64_t part_words = 0;
+    if (fused) {
+        int txi = 0;
+        for (int l = 0; l < L; ++l) {
+            while (txi + 1 < ntx && l >= P->htx[txi].lat0 + P->htx[txi].nlat) ++txi;
+            LatDesc& D = P->hdesc[l];
+            const int64_t fn = P->htx[txi].fn, words = D.bm_words;
+            rt_words = std::max<int>(rt_words, (int)words);
+            int64_t pc = std::min<int64_t>((384 + L - 1) / L, std::max<int64_t>(1, fn / (2 * words)));
+            pc = std::max<int64_t>(1, std::min<int64_t>(pc, (fn + 1023) / 1024));
+            const int64_t ch = (fn + pc - 1) / pc;
+            D.rt0 = (int32_t)rtiles.size();
+            for (int64_t k0 = 0; k0 < fn; k0 += ch) {
+                rtiles.push_back(ResTile{P->htx[txi].foff + k0, P->htx[txi].foff + std::min(fn, k0 + ch), part_words,
+                                         l, txi});
+                part_words += 2 * words;
+            }
+            if (fn == 0) {   // one empty tile still clears the bitmaps
+                rtiles.push_back(ResTile{P->htx[txi].foff, P->htx[txi].foff, part_words, l, txi});
+                part_words += 2 * words;
+            }
+            D.rtn = (int32_t)rtiles.size() - D.rt0;
+        }
+        MR1L_HIP_TRY(P->desc.upload(P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
+        MR1L_HIP_TRY(P->rtiles.upload(rtiles.data(), rtiles.size() * sizeof(ResTile)));
+        MR1L_HIP_TRY(P->part.alloc((size_t)std::max<int64_t>(1, part_words) * sizeof(uint32_t)));
+    }
     MR1L_HIP_TRY(P->res32.alloc((size_t)std::max<int64_t>(1, (int64_t)max_nlat * n) * sizeof(int32_t)));
     MR1L_HIP_TRY(P->bitmaps.alloc((size_t)std::max<int64_t>(1, P->bm_total) * sizeof(uint32_t)));
     const Plan* sh = sp.share_filters;
@@ -250,6 +306,12 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     a.res32 = P->res32.as<int32_t>();
     a.hist = P->hist.as<HistTile>();
     a.nhist = (int)tiles.size();
+    a.hist_words = hist_words;
+    a.fused = fused;
+    a.rtiles = P->rtiles.as<ResTile>();
+    a.nrt = (int)rtiles.size();
+    a.rt_words = rt_words;
+    a.part = P->part.as<uint32_t>();
 
     if (!twiddles<T>(sp.device) || !twiddles<double>(sp.device)) {
         set_error("could not allocate twiddle tables");
@@ -328,12 +390,12 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
             if (g.small) {
                 tm.begin(1);
                 launch_bluestein_small<T>(a, g, yc, a.samp_stride, true, work, filt, work, a.work_stride, false, -1,
-                                          !eval, s);
+                                          !eval, false, s);
                 tm.end();
                 continue;
             }
             tm.begin(2);
-            launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, s);
+            launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, false, s);
             tm.end();
             tm.begin(3);
             launch_p2<T>(a, g, work, filt, -1, s);
@@ -365,19 +427,19 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
         const cx<T>* cc = c + r0 * a.n;
         cx<T>* yc = y + r0 * a.samp_stride;
         tm.begin(6);
-        launch_clear_bins<T>(a, work, s);
+        if (eval) launch_clear_bins<T>(a, work, s);
         launch_scatter<T>(a, cc, work, eval, s);
         tm.end();
         for (const FftGroup& g : p->groups) {
             if (g.small) {
                 tm.begin(1);
                 launch_bluestein_small<T>(a, g, work, a.work_stride, false, work, filt, yc, a.samp_stride, true, +1,
-                                          !eval, s);
+                                          !eval, !eval, s);
                 tm.end();
                 continue;
             }
             tm.begin(2);
-            launch_p1<T>(a, g, work, a.work_stride, false, work, +1, s);
+            launch_p1<T>(a, g, work, a.work_stride, false, work, +1, !eval, s);
             tm.end();
             tm.begin(3);
             launch_p2<T>(a, g, work, filt, +1, s);
