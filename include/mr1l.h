@@ -121,6 +121,14 @@ mr1l_status mr1l_alias(mr1l_plan_t plan, int64_t* residues, uint8_t* unaliased, 
 mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_uncovered,
                       int64_t* fft_lengths);
 
+/* Plan-cached index work.  The residues r_l(k) and the alias bitmaps of Alg. 2 depend only on I
+ * and the lattices, not on the samples or coefficients.  By default every forward and adjoint call
+ * recomputes them (Alg. 2 as stated).  With enable = 1 the next call computes them once and later
+ * calls reuse them; enable = 0 restores recomputation.  Host-side state, not ordered with
+ * streams: a HIP graph captured while caching is on contains no index kernels.
+ * Errors: MR1L_ERR_ARG for a NULL plan. */
+mr1l_status mr1l_cache_alias(mr1l_plan_t plan, int enable);
+
 /* Release a plan and its device memory (NULL is accepted). */
 mr1l_status mr1l_destroy(mr1l_plan_t plan);
 

@@ -80,16 +80,6 @@ template <> __device__ __forceinline__ cx<double> cispi<double>(double x) {
     return {c, s};
 }
 
-// e^{-2 pi i e / 2^lgN} for 0 <= e < 2^lgN <= 2^24; the argument -2e/2^lgN is exact in T.
-template <typename T>
-__device__ __forceinline__ cx<T> tw_pow2(uint32_t e, int lgN) {
-    T s, c;
-    const T x = -(T)e * (T)ldexp(1.0, 1 - lgN);
-    if constexpr (sizeof(T) == 4) sincospif(x, &s, &c);
-    else sincospi(x, &s, &c);
-    return {c, s};
-}
-
 // (n^2 mod 2M) as an integer-valued double: every intermediate is an integer below 2^53 for
 // n < 2^23, so the remainder is exact after at most one correction of the quotient estimate.
 __device__ __forceinline__ double sq_mod_2M(int64_t n, int64_t M, double inv2M) {
@@ -101,10 +91,62 @@ __device__ __forceinline__ double sq_mod_2M(int64_t n, int64_t M, double inv2M) 
     return q;
 }
 
+// Single precision phases: e^{-2 pi i (idx/256)} from a 256-entry table in LDS times e^{-i th}
+// for a residual angle |th| <= pi/256, with cos th = 1 - th^2/2 and sin th = th (1 - th^2/6)
+// (dropped terms below 1e-9).  The integer part of the phase is reduced exactly before th is
+// formed, so the result is accurate to a few ulp at any index.
+constexpr int kPhLg = 8;
+template <typename T> struct PhaseTab { static constexpr int n = sizeof(T) == 4 ? (1 << kPhLg) : 1; };
+
+// ph[m] = e^{-2 pi i m/256} (every thread of the workgroup takes part; a barrier must follow)
+template <typename T>
+__device__ __forceinline__ void phase_fill(cx<T>* ph) {
+    if constexpr (sizeof(T) == 4) {
+        for (int m = threadIdx.x; m < (1 << kPhLg); m += blockDim.x) {
+            float sn, c;
+            sincospif(-(float)m * (2.0f / (1 << kPhLg)), &sn, &c);   // exact argument
+            ph[m] = {c, sn};
+        }
+    }
+}
+
+__device__ __forceinline__ cx<float> tw_rot(const cx<float>* ph, int idx, float th) {
+    const cx<float> t = ph[idx & ((1 << kPhLg) - 1)];
+    const float t2 = th * th;
+    const float c = fmaf(-0.5f, t2, 1.0f);
+    const float sn = th * fmaf(-t2, 1.0f / 6.0f, 1.0f);
+    return {t.x * c + t.y * sn, t.y * c - t.x * sn};
+}
+
+// e^{-2 pi i e / 2^lgN} for 0 <= e < 2^lgN <= 2^24 (ph: the LDS phase table, single precision)
+template <typename T>
+__device__ __forceinline__ cx<T> tw_pow2(uint32_t e, int lgN, const cx<T>* ph) {
+    if constexpr (sizeof(T) == 4) {
+        if (lgN <= kPhLg) return ph[e << (kPhLg - lgN)];
+        const int sh = lgN - kPhLg;
+        const uint32_t idx = (e + (1u << (sh - 1))) >> sh;
+        const int rem = (int)e - (int)(idx << sh);
+        return tw_rot(ph, (int)idx, (float)rem * (float)(6.283185307179586 / (double)(1 << lgN)));
+    } else {
+        T s, c;
+        const T x = -(T)e * (T)ldexp(1.0, 1 - lgN);   // exact
+        sincospi(x, &s, &c);
+        return {c, s};
+    }
+}
+
 // e^{sign i pi (n^2 mod 2M)/M}
 template <typename T>
-__device__ __forceinline__ cx<T> chirp(int64_t n, int64_t M, double invM, int sign) {
-    return cispi<T>((double)sign * (sq_mod_2M(n, M, 0.5 * invM) * invM));
+__device__ __forceinline__ cx<T> chirp(int64_t n, int64_t M, double invM, int sign, const cx<T>* ph) {
+    const double q = sq_mod_2M(n, M, 0.5 * invM);
+    if constexpr (sizeof(T) == 4) {
+        // e^{sign i pi q/M} = e^{-2 pi i tau/256}, tau = -sign q 128/M
+        const double tau = (double)(-sign) * q * ((double)(1 << (kPhLg - 1)) * invM);
+        const double id = rint(tau);
+        return tw_rot(ph, (int)id, (float)(tau - id) * (float)(6.283185307179586 / (1 << kPhLg)));
+    } else {
+        return cispi<T>((double)sign * (q * invM));
+    }
 }
 
 // bin m of lattice D holds exactly one frequency: seen and not multi in the alias bitmaps
@@ -364,6 +406,9 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
     constexpr int LR0 = stage_lr(LGN1, 0, true), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
     constexpr int LRL = stage_lr(LGN1, NS - 1, true), RL = 1 << LRL, LGNBL = LGN1 - LRL;
     __shared__ cx<T> lds[Padded<(1 << kTileLg) + C>::v];
+    __shared__ cx<T> ph[PhaseTab<T>::n];
+    phase_fill<T>(ph);
+    __syncthreads();
     const int li = blockIdx.x >> TPL_LG;
     const int c0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGC;
     const LatDesc D = a.desc[lat[li]];
@@ -382,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
             cx<T> x = {(T)0, (T)0};
             if (n < nvalid) {
                 x = in[n];
-                if (SRC != 2) x = cmul(x, chirp<T>(n, D.M, D.invM, sign));
+                if (SRC != 2) x = cmul(x, chirp<T>(n, D.M, D.invM, sign, ph));
                 if (SRC == 3 && !owned_bin(a.bitmaps, D, n)) x = {(T)0, (T)0};
             }
             v[u * R0 + r] = x;
@@ -395,8 +440,8 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
         int col, j;
         bfly<LGNBL, C, true>(u, col, j);
         const int n2 = c0 + col;
-        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN);
-        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNBL) & ((1 << LGN) - 1)), LGN);
+        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
+        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNBL) & ((1 << LGN) - 1)), LGN, ph);
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k1 = j + (r << LGNBL);
@@ -481,6 +526,9 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
     constexpr int LR0 = stage_lr(LGN1, 0, false), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
     constexpr int LRL = stage_lr(LGN1, NS - 1, false), RL = 1 << LRL, LGNBL = LGN1 - LRL;
     __shared__ cx<T> lds[Padded<(1 << kTileLg) + C>::v];
+    __shared__ cx<T> ph[PhaseTab<T>::n];
+    phase_fill<T>(ph);
+    __syncthreads();
     const int li = blockIdx.x >> TPL_LG;
     const int c0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGC;
     const LatDesc D = a.desc[lat[li]];
@@ -492,8 +540,8 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
         int col, j;
         bfly<LGNB0, C, true>(u, col, j);
         const int n2 = c0 + col;
-        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN);
-        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNB0) & ((1 << LGN) - 1)), LGN);
+        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
+        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNB0) & ((1 << LGN) - 1)), LGN, ph);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k1 = j + (r << LGNB0);
@@ -514,7 +562,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
         for (int r = 0; r < RL; ++r) {
             const int n1 = j + (r << LGNBL);
             const int64_t n = ((int64_t)n1 << LGN2) + c0 + col;
-            if (n < D.M) out[n] = cscale(cmul(v[u * RL + r], chirp<T>(n, D.M, D.invM, sign)), sc);
+            if (n < D.M) out[n] = cscale(cmul(v[u * RL + r], chirp<T>(n, D.M, D.invM, sign, ph)), sc);
         }
     }
 }
@@ -528,12 +576,15 @@ __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const int* __restr
                                                     const cx<T>* __restrict__ tw) {
     constexpr int N = 1 << LGN;
     __shared__ cx<T> lds[Padded<N>::v];
+    __shared__ cx<T> ph[PhaseTab<T>::n];
+    phase_fill<T>(ph);
+    __syncthreads();
     const LatDesc D = a.desc[lat[blockIdx.x]];
     const int64_t rhs = blockIdx.y;
     const cx<T>* in = src + rhs * src_stride + (SRC_SAMPLES ? D.samp_off : D.work_off);
     for (int n = threadIdx.x; n < N; n += kThreads) {
         cx<T> v = {(T)0, (T)0};
-        if (n < D.M) v = cmul(in[n], chirp<T>(n, D.M, D.invM, sign));
+        if (n < D.M) v = cmul(in[n], chirp<T>(n, D.M, D.invM, sign, ph));
         if (!SRC_SAMPLES && mask_bins && n < D.M && !owned_bin(a.bitmaps, D, n)) v = {(T)0, (T)0};
         lds[pidx(n)] = v;
     }
@@ -547,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void k_small(TxArgs a, const int* __restr
     cx<T>* out = TO_SAMPLES ? dst + rhs * dst_stride + D.samp_off : work + rhs * a.work_stride + D.work_off;
     const T sc = scale_by_invM ? (T)D.invM : (T)1;
     for (int n = threadIdx.x; n < D.M; n += kThreads)
-        out[n] = cscale(cmul(lds[pidx(n)], chirp<T>(n, D.M, D.invM, sign)), sc);
+        out[n] = cscale(cmul(lds[pidx(n)], chirp<T>(n, D.M, D.invM, sign, ph)), sc);
 }
 
 // plain in-place forward DFT of a whole region (filter construction on the one-block path)

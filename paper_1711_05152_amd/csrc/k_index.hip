@@ -151,7 +151,9 @@ __global__ __launch_bounds__(kResThreads) void k_res_hist(TxArgs a) {
 }
 
 // bitmaps of lattice blockIdx.y from its partial bitmaps (consecutive, 2 bm_words apart): multi =
-// some partial multi, or seen in two partials
+// some partial multi, or seen in two partials.  (A last-arriving-workgroup merge inside the fused
+// kernel needs an agent-scope release per workgroup, i.e. an L2 writeback each, which costs more
+// than this separate launch.)
 __global__ __launch_bounds__(256) void k_hist_merge(TxArgs a) {
     const LatDesc D = a.desc[blockIdx.y];
     const int64_t words = D.bm_words;

@@ -372,15 +372,22 @@ struct StageTimer {
     }
 };
 
+// residues (and, for Alg. 2's weights, the alias bitmaps) of every lattice, unless cached
+static void index_pass(Plan* p, bool eval, StageTimer& tm, hipStream_t s) {
+    if (p->cache_alias && p->alias_valid) return;
+    tm.begin(0);
+    launch_alias(p->args, !eval, s);
+    tm.end();
+    p->alias_valid = p->cache_alias;
+}
+
 template <typename T>
 static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
-    tm.begin(0);
-    launch_alias(p->args, !eval, s);
-    tm.end();
+    index_pass(p, eval, tm, s);
     for (int64_t r0 = 0; r0 < p->n_rhs; r0 += p->rhs_chunk) {
         TxArgs a = p->args;
         a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
@@ -418,9 +425,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
-    tm.begin(0);
-    launch_alias(p->args, !eval, s);
-    tm.end();
+    index_pass(p, eval, tm, s);
     for (int64_t r0 = 0; r0 < p->n_rhs; r0 += p->rhs_chunk) {
         TxArgs a = p->args;
         a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
@@ -465,6 +470,7 @@ mr1l_status plan_adjoint(Plan* p, const void* coeffs, void* samples, hipStream_t
 
 mr1l_status plan_alias(Plan* p, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s) {
     launch_alias(p->args, true, s);
+    p->alias_valid = p->cache_alias;
     launch_alias_export(p->args, res, uniq, counter, s);
     MR1L_HIP_TRY(hipGetLastError());
     return MR1L_OK;
@@ -623,6 +629,18 @@ mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_unco
     }
     return MR1L_OK;
     MR1L_GUARD_END
+}
+
+mr1l_status mr1l_cache_alias(mr1l_plan_t plan, int enable) {
+    clear_error();
+    if (!plan) {
+        set_error("plan is NULL");
+        return MR1L_ERR_ARG;
+    }
+    Plan* p = (Plan*)plan;
+    p->cache_alias = enable != 0;
+    p->alias_valid = false;
+    return MR1L_OK;
 }
 
 mr1l_status mr1l_destroy(mr1l_plan_t plan) {

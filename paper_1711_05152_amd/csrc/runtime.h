@@ -140,6 +140,9 @@ struct Plan {
     std::vector<FftGroup> groups;   // lattices grouped by Bluestein length
     void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};
+    // plan-cached index work: residues and bitmaps valid from an earlier call
+    bool cache_alias = false;
+    bool alias_valid = false;
     // per-stage timing
     bool timing = false;
     struct Rec { int stage; hipEvent_t a, b; };

@@ -131,6 +131,11 @@ class Plan:
         return g
 
     # -- timing -----------------------------------------------------------------------------------
+    def cache_alias(self, enable: bool = True) -> None:
+        """Reuse the residues and alias bitmaps between calls (they depend only on the frequency
+        set and the lattices); off by default, where every call recomputes them as Alg. 2 does."""
+        check(lib().mr1l_cache_alias(self._h, int(enable)), "mr1l_cache_alias")
+
     def timing(self, enable: bool = True) -> None:
         check(lib().mr1l_timing_enable(self._h, int(enable)), "mr1l_timing_enable")
 

@@ -180,3 +180,30 @@ def test_exact_modulo_path():
     r0, u0, c0 = O.unaliased_sets(freqs, M, z)
     assert np.array_equal(res.cpu().numpy(), r0)
     assert np.array_equal(cnt.cpu().numpy().astype(np.int64), c0)
+
+
+@pytest.mark.parametrize("weights", ["paper", "eval"])
+def test_cache_alias_matches_recompute(weights):
+    """Plan-cached index work (residues and bitmaps reused between calls) gives the results of
+    recomputing them in every call, across several calls: bit-identical where the kernels are
+    deterministic; the Fourier-matrix adjoint accumulates bins with floating-point atomics, whose
+    order (and so the last bits) may change from call to call, so it is compared to 1e-5."""
+    torch = require_gpu()
+    p = transform_problem(rng_for(310), 5000, 7, 25, 9, 5000, 10000, n_rhs=2)
+    ref = _plan(p, "c64", weights)
+    cached = _plan(p, "c64", weights)
+    cached.cache_alias(True)
+    y = _to(torch, p.samples, "c64")
+    c = _to(torch, p.coeffs, "c64")
+
+    def same_adj():
+        a, b = cached.adjoint(c), ref.adjoint(c)
+        if weights == "paper":
+            return torch.equal(a, b)
+        return float((a - b).abs().max()) <= 1e-5 * float(b.abs().max())
+
+    for _ in range(3):
+        assert torch.equal(cached.forward(y), ref.forward(y))
+        assert same_adj()
+    cached.cache_alias(False)
+    assert same_adj()
