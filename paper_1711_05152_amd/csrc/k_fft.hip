@@ -12,9 +12,12 @@
 //    stage 3 = inverse twiddles + inverse column DFTs + output chirp.  Stage 2 is where forward
 //    and inverse transforms meet, so the filter spectrum is stored in that stage's layout and the
 //    intermediate never needs a transpose.
-// All in-LDS DFTs are Stockham radix-8 (+ one radix-2/4 stage) with twiddles from a table, with
-// every length a compile-time constant: lattices are grouped by convolution length and each
-// group is launched with kernels specialised for its sizes.
+// The tile DFTs of the four-step path are Stockham stages of radix up to 16 whose first and last
+// stages work on registers (only the exchanges between stages go through LDS); the one-block path
+// uses radix-8 stages in LDS.  Stage twiddles come from a table; single-precision chirps and
+// four-step twiddles from a 256-entry LDS table plus a small-angle rotation.  Every length is a
+// compile-time constant: lattices are grouped by convolution length and each group is launched
+// with kernels specialised for its sizes.
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -207,6 +210,54 @@ template <typename T, int SIGN> struct Dft<T, 8, SIGN> {
 };
 
 
+// x * e^{SIGN 2 pi i E/16} for a compile-time E
+template <typename T, int SIGN, int E>
+__device__ __forceinline__ cx<T> rot16(cx<T> x) {
+    constexpr int e = E & 15;
+    if constexpr (e == 0) return x;
+    else if constexpr (e == 4) return mul_si<T, SIGN>(x);
+    else if constexpr (e == 8) return cx<T>{-x.x, -x.y};
+    else if constexpr (e == 12) return mul_si<T, -SIGN>(x);
+    else {
+        // cos and sin of 2 pi e / 16
+        constexpr double C1 = 0.923879532511286756128183189396788933, S1 = 0.382683432365089771728459984030398866;
+        constexpr double C2 = 0.707106781186547524400844362104849039;
+        constexpr double cs[16] = {1, C1, C2, S1, 0, -S1, -C2, -C1, -1, -C1, -C2, -S1, 0, S1, C2, C1};
+        constexpr double sn[16] = {0, S1, C2, C1, 1, C1, C2, S1, 0, -S1, -C2, -C1, -1, -C1, -C2, -S1};
+        const T wc = (T)cs[e], ws = (T)(SIGN * sn[e]);
+        return {x.x * wc - x.y * ws, x.x * ws + x.y * wc};
+    }
+}
+
+// radix 16 as 4 x 4: DFT-4 over the residues mod 4, twiddles w16^{m k1}, DFT-4 across
+template <typename T, int SIGN> struct Dft<T, 16, SIGN> {
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        cx<T> a[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[m][q] = v[m + 4 * q];
+            Dft<T, 4, SIGN>::run(a[m]);
+        }
+        a[1][1] = rot16<T, SIGN, 1>(a[1][1]);
+        a[1][2] = rot16<T, SIGN, 2>(a[1][2]);
+        a[1][3] = rot16<T, SIGN, 3>(a[1][3]);
+        a[2][1] = rot16<T, SIGN, 2>(a[2][1]);
+        a[2][2] = rot16<T, SIGN, 4>(a[2][2]);
+        a[2][3] = rot16<T, SIGN, 6>(a[2][3]);
+        a[3][1] = rot16<T, SIGN, 3>(a[3][1]);
+        a[3][2] = rot16<T, SIGN, 6>(a[3][2]);
+        a[3][3] = rot16<T, SIGN, 9>(a[3][3]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            Dft<T, 4, SIGN>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+
 // ---- Stockham stages with compile-time sizes -------------------------------------------------------
 // NSEQ sequences of length 2^LGN stored at buf[pidx(b*S + e)].  2^LGNS is the length of the
 // sub-transforms already done; this stage has radix 2^LR.
@@ -277,11 +328,14 @@ __device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw)
 // A tile holds NSEQ sequences of 2^LGN values (NSEQ * 2^LGN = 4096): every thread owns 16 values
 // of each stage.  The first stage takes its inputs from registers (the caller loads them from
 // global memory in that stage's order) and the last stage leaves its outputs in registers (the
-// caller stores them), so only the exchanges between stages go through LDS.  Radix 8 everywhere
-// except one radix-2/4 stage, placed first (REMF) or last.
-constexpr int n_stages(int lgn) { return lgn / 3 + ((lgn % 3) ? 1 : 0); }
+// caller stores them), so only the exchanges between stages go through LDS.  As few stages as
+// radix 16 allows (ceil(lgn/4)), the bits spread evenly over them: descending radices, or
+// ascending ones when REMF (so a forward transform with REMF and an inverse without meet at
+// stages of the same radix, e.g. 1024 = 8 8 16 | 16 8 8).
+constexpr int n_stages(int lgn) { return (lgn + 3) / 4; }
 constexpr int stage_lr(int lgn, int i, bool remf) {
-    return (lgn % 3) == 0 ? 3 : (remf ? (i == 0 ? lgn % 3 : 3) : (i == n_stages(lgn) - 1 ? lgn % 3 : 3));
+    return remf ? (i >= n_stages(lgn) - lgn % n_stages(lgn) ? lgn / n_stages(lgn) + 1 : lgn / n_stages(lgn))
+                : (i < lgn % n_stages(lgn) ? lgn / n_stages(lgn) + 1 : lgn / n_stages(lgn));
 }
 constexpr int stage_lgns(int lgn, int i, bool remf) {
     int s = 0;
@@ -330,6 +384,11 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict_
                 w[5] = cmul(w[1], w[4]);
                 w[6] = cmul(w[2], w[4]);
                 w[7] = cmul(w[3], w[4]);
+            }
+            if constexpr (R >= 16) {
+                w[8] = tw[8 * step];
+#pragma unroll
+                for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
             }
 #pragma unroll
             for (int r = 1; r < R; ++r) x[r] = SIGN < 0 ? cmul(x[r], w[r]) : cmulc(x[r], w[r]);
@@ -453,8 +512,8 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
 
 // ---- four-step stage 2 -----------------------------------------------------------------------------
 // One tile = 2^(12 - LGN2) rows.  CONV: row DFT, multiply by the filter (conjugated for sign +1),
-// inverse row DFT (the forward's last stage and the inverse's first stage are both radix 8 over
-// the same elements, so the product never leaves the registers); else row DFT only.
+// inverse row DFT (the forward's last stage and the inverse's first stage have the same radix and
+// hold the same elements, so the product never leaves the registers); else row DFT only.
 template <typename T, int LGN, bool CONV>
 __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
                                                  const cx<T>* __restrict__ filt, int sign,
@@ -463,10 +522,11 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
     constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2;
     constexpr int TPL_LG = LGN - kTileLg;
     constexpr int LR0 = stage_lr(LGN2, 0, true), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
-    constexpr int LGNB8 = LGN2 - 3;            // forward last / inverse first stage: radix 8
     constexpr int NSI = n_stages(LGN2);
+    constexpr int LRM = stage_lr(LGN2, NSI - 1, true), RM = 1 << LRM;   // forward last = inverse first
+    constexpr int LGNBM = LGN2 - LRM;
     constexpr int LRL = stage_lr(LGN2, NSI - 1, false), RL = 1 << LRL, LGNBL = LGN2 - LRL;
-    static_assert(stage_lr(LGN2, n_stages(LGN2) - 1, true) == 3 && stage_lr(LGN2, 0, false) == 3, "radix 8 meet");
+    static_assert(stage_lr(LGN2, 0, false) == LRM, "the forward's last and the inverse's first stage must match");
     __shared__ cx<T> lds[Padded<(1 << kTileLg)>::v];
     const int li = blockIdx.x >> TPL_LG;
     const int r0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGR;
@@ -485,13 +545,13 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
     if constexpr (CONV) {
         const cx<T>* f = filt + D.filt_off + ((int64_t)r0 << LGN2);
 #pragma unroll
-        for (int u = 0; u < kVals / 8; ++u) {
+        for (int u = 0; u < kVals / RM; ++u) {
             int b, j;
-            bfly<LGNB8, ROWS, false>(u, b, j);
+            bfly<LGNBM, ROWS, false>(u, b, j);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const cx<T> fv = f[(b << LGN2) + j + (r << LGNB8)];
-                v[u * 8 + r] = sign < 0 ? cmul(v[u * 8 + r], fv) : cmulc(v[u * 8 + r], fv);
+            for (int r = 0; r < RM; ++r) {
+                const cx<T> fv = f[(b << LGN2) + j + (r << LGNBM)];
+                v[u * RM + r] = sign < 0 ? cmul(v[u * RM + r], fv) : cmulc(v[u * RM + r], fv);
             }
         }
         fft_regs<T, LGN2, ROWS, N2, +1, false, false, false>(lds, v, tw);
@@ -504,11 +564,11 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < kVals / 8; ++u) {
+        for (int u = 0; u < kVals / RM; ++u) {
             int b, j;
-            bfly<LGNB8, ROWS, false>(u, b, j);
+            bfly<LGNBM, ROWS, false>(u, b, j);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) w[(b << LGN2) + j + (r << LGNB8)] = v[u * 8 + r];
+            for (int r = 0; r < RM; ++r) w[(b << LGN2) + j + (r << LGNBM)] = v[u * RM + r];
         }
     }
 }
