@@ -79,6 +79,13 @@ struct ResTile {
     int32_t l, tx;
 };
 constexpr int kFusedMaxWords = 1 << 14;   // bitmaps of up to 2^19 bins (2 x 64 KiB of LDS)
+constexpr int kResThreads = 1024;         // threads of a fused-pass workgroup
+// residues per thread and iteration of the fused pass for padded width DP (0: 64-bit path), all
+// their component loads in flight together within the 128 VGPRs of a 1024-thread workgroup; a
+// ResTile holds kResThreads * res_unroll(DP) frequencies, one iteration
+__host__ __device__ constexpr int res_unroll(int dp) {
+    return dp == 0 ? 4 : (dp <= 8 ? 8 : (dp <= 12 ? 6 : (dp <= 16 ? 4 : 2)));
+}
 
 // Frequencies are kept component-major (structure of arrays) in the narrowest signed integer
 // type that holds them.
@@ -130,7 +137,8 @@ struct TxArgs {
     int64_t work_stride;      // elements per rhs in the work area
     uint32_t* bitmaps;        // device alias bitmaps
     int64_t bm_total;         // words of all bitmaps
-    int32_t* res32;           // device residues [max_nlat][n] (slot = lattice index within its transform)
+    int32_t* res32;           // device residues [max_nlat][rs] (slot = lattice index within its transform)
+    int64_t rs;               // row stride of res32: n rounded up to a multiple of 4 (16-byte rows)
     const HistTile* hist;     // device [nhist] (l = -1: idle slot of the XCD-interleaved order)
     int nhist;
     int hist_words;           // largest bitmap words of one tile (LDS per bitmap)

@@ -37,24 +37,32 @@ __global__ __launch_bounds__(256) void k_residues(TxArgs a) {
     const int j = blockIdx.y;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
         const TxDesc t = get_tx<SINGLE>(a, g);
-        if (j < t.nlat) a.res32[(int64_t)j * a.n + g] = (int32_t)residue<K>(a, a.desc[t.lat0 + j], g);
+        if (j < t.nlat) a.res32[(int64_t)j * a.rs + g] = (int32_t)residue<K>(a, a.desc[t.lat0 + j], g);
     }
 }
 
-// 32-bit path: one thread per frequency, its d components loaded once into registers and every
-// lattice of its transform done in turn.  Products of 24-bit operands wrap modulo 2^32, which is
-// exact because the plan checked |k . z| < 2^31; the quotient estimate in double is off by at
-// most one and the remainder s - qM is exact in double.
+// 32-bit path: one thread per (frequency, group of kResLat lattice slots), its d components loaded
+// once into registers.  Products of 24-bit operands wrap modulo 2^32, which is exact because the
+// plan checked |k . z| < 2^31; the quotient estimate in double is off by at most one and the
+// remainder s - qM is exact in double.  z rows are zero-padded to DP entries, so components past
+// d (loaded from the clamped address of the last one) contribute nothing and every load is
+// unconditional (all of them in flight together).
+constexpr int kResLat = 4;
 template <typename K, int DP, bool SINGLE>
 __global__ __launch_bounds__(256) void k_residues_narrow(TxArgs a) {
     const K* __restrict__ f = (const K*)a.fv.f;
     const int dl = a.fv.d - 1;
+    const int j0 = blockIdx.y * kResLat;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
         const TxDesc t = get_tx<SINGLE>(a, g);
+        if (j0 >= t.nlat) continue;
         int kv[DP];
 #pragma unroll
-        for (int c = 0; c < DP; ++c) kv[c] = (int)f[(int64_t)min(c, dl) * a.fv.nf + g];
-        for (int j = 0; j < t.nlat; ++j) {
+        for (int c = 0; c < DP; ++c) kv[c] = (int)(f + (int64_t)min(c, dl) * a.fv.nf)[(uint32_t)g];
+#pragma unroll
+        for (int jj = 0; jj < kResLat; ++jj) {
+            const int j = j0 + jj;
+            if (j >= t.nlat) break;
             const int l = t.lat0 + j;
             const int32_t* __restrict__ zz = a.z32 + (int64_t)l * a.zrow;
             int s = 0;
@@ -65,7 +73,7 @@ __global__ __launch_bounds__(256) void k_residues_narrow(TxArgs a) {
             int r = (int)fma(-q, (double)M, (double)s);
             r += r < 0 ? M : 0;
             r -= r >= M ? M : 0;
-            a.res32[(int64_t)j * a.n + g] = r;
+            a.res32[(int64_t)j * a.rs + g] = r;
         }
     }
 }
@@ -95,8 +103,7 @@ __device__ __forceinline__ int residue_narrow(const TxArgs& a, const int* zr, in
 // r_l(k) for its chunk of frequencies, stores them, and counts them into LDS bitmaps covering all
 // bins of lattice l (2-bit saturating counts: seen, multi); the partial bitmaps are written out
 // whole and combined by k_hist_merge.
-constexpr int kResThreads = 512;
-constexpr int kResUnroll = 4;
+
 
 template <typename K, int DP>
 __global__ __launch_bounds__(kResThreads) void k_res_hist(TxArgs a) {
@@ -113,13 +120,14 @@ __global__ __launch_bounds__(kResThreads) void k_res_hist(TxArgs a) {
         multi[w] = 0u;
     }
     __syncthreads();
-    int32_t* res = a.res32 + (int64_t)j * a.n;
+    int32_t* res = a.res32 + (int64_t)j * a.rs;
     const int64_t last = rt.k1 - 1;
     constexpr int DZ = DP > 0 ? DP : 1;
     int zr[DZ];
 #pragma unroll
     for (int c = 0; c < DZ; ++c) zr[c] = DP > 0 ? a.z32[(int64_t)rt.l * a.zrow + c] : 0;
     const int M = (int)D.M;
+    constexpr int kResUnroll = res_unroll(DP);
     for (int64_t kb = rt.k0 + threadIdx.x; kb < rt.k1; kb += kResThreads * kResUnroll) {
         int r[kResUnroll];
 #pragma unroll
@@ -184,8 +192,22 @@ __global__ __launch_bounds__(256) void k_hist_merge(TxArgs a) {
     }
 }
 
-constexpr int kHistThreads = 512;
-constexpr int kHistUnroll = 16;
+constexpr int kHistThreads = 1024;
+constexpr int kHistVec = 4;   // 16-byte residue loads in flight per thread and iteration
+
+// Alias histogram of one bin range [m0, m1) of lattice l (Alg. 2, definition of I_l): the
+// workgroup streams all residues of the lattice (16-byte loads; the row is 16-byte aligned) and
+// counts those in its range into LDS bitmaps (2-bit saturating counts: seen, multi), then writes
+// its words out whole.  Ranges of one lattice sit on workgroup slots of the same XCD, so the
+// residue row is fetched into one L2 only.
+__device__ __forceinline__ void hist_count(uint32_t* seen, uint32_t* multi, int32_t v, int32_t m0, uint32_t span,
+                                           uint32_t& old, uint32_t& rr) {
+    rr = (uint32_t)(v - m0);
+    old = rr < span ? atomicOr(&seen[rr >> 5], 1u << (rr & 31)) : 0u;
+}
+__device__ __forceinline__ void hist_multi(uint32_t* multi, uint32_t old, uint32_t rr) {
+    if ((old >> (rr & 31)) & 1u) atomicOr(&multi[rr >> 5], 1u << (rr & 31));
+}
 
 // LDS: seen[hist_words] then multi[hist_words] (dynamic)
 __global__ __launch_bounds__(kHistThreads) void k_hist_lds(TxArgs a) {
@@ -203,22 +225,39 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(TxArgs a) {
         multi[w] = 0u;
     }
     __syncthreads();
-    const int32_t* r = a.res32 + (int64_t)(h.l - t.lat0) * a.n + t.foff;
-    const int64_t last = t.fn - 1;
-    for (int64_t k0 = threadIdx.x; k0 < t.fn; k0 += kHistThreads * kHistUnroll) {
-        // straight-line loads (clamped addresses) so that all of them are in flight together
-        int32_t v[kHistUnroll];
+    const int32_t* row = a.res32 + (int64_t)(h.l - t.lat0) * a.rs;
+    const int64_t k0 = t.foff, k1 = t.foff + t.fn;
+    const int64_t a0 = std::min<int64_t>((k0 + 3) & ~(int64_t)3, k1);
+    const int64_t a1 = std::max<int64_t>(a0, k1 & ~(int64_t)3);
+    // unaligned head [k0, a0) and tail [a1, k1): at most 3 residues each
+    if (threadIdx.x < a0 - k0 || threadIdx.x < k1 - a1) {
+        uint32_t o0 = 0, r0 = span, o1 = 0, r1 = span;
+        if (threadIdx.x < a0 - k0) hist_count(seen, multi, row[k0 + threadIdx.x], h.m0, span, o0, r0);
+        if (threadIdx.x < k1 - a1) hist_count(seen, multi, row[a1 + threadIdx.x], h.m0, span, o1, r1);
+        if (r0 < span) hist_multi(multi, o0, r0);
+        if (r1 < span) hist_multi(multi, o1, r1);
+    }
+    const int4* v4 = (const int4*)(row + a0);
+    const int64_t nv = (a1 - a0) >> 2;
+    for (int64_t i = threadIdx.x; i < nv; i += kHistThreads * kHistVec) {
+        int4 q[kHistVec];
 #pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u) v[u] = r[min(k0 + (int64_t)u * kHistThreads, last)];
-        uint32_t rr[kHistUnroll], old[kHistUnroll];
+        for (int u = 0; u < kHistVec; ++u) q[u] = v4[std::min<int64_t>(i + u * kHistThreads, nv - 1)];   // clamped
+        uint32_t old[4 * kHistVec], rr[4 * kHistVec];
 #pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u) {
-            rr[u] = (k0 + (int64_t)u * kHistThreads <= last) ? (uint32_t)(v[u] - h.m0) : span;
-            old[u] = rr[u] < span ? atomicOr(&seen[rr[u] >> 5], 1u << (rr[u] & 31)) : 0u;
+        for (int u = 0; u < kHistVec; ++u) {
+            const bool ok = i + u * kHistThreads < nv;
+            const int32_t e[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                rr[4 * u + c] = span;
+                old[4 * u + c] = 0u;
+                if (ok) hist_count(seen, multi, e[c], h.m0, span, old[4 * u + c], rr[4 * u + c]);
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kHistUnroll; ++u)
-            if (rr[u] < span && ((old[u] >> (rr[u] & 31)) & 1u)) atomicOr(&multi[rr[u] >> 5], 1u << (rr[u] & 31));
+        for (int u = 0; u < 4 * kHistVec; ++u)
+            if (rr[u] < span) hist_multi(multi, old[u], rr[u]);
     }
     __syncthreads();
     uint32_t* gs = a.bitmaps + D.bm_off + (h.m0 >> 5);
@@ -237,7 +276,7 @@ __device__ __forceinline__ uint32_t unaliased_chunk(const TxArgs& a, const TxDes
                                                     int32_t* r) {
     const int jl = t.nlat - 1;
 #pragma unroll
-    for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, jl) * a.n + g];
+    for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, jl) * a.rs + g];
     uint32_t w[LC];
 #pragma unroll
     for (int u = 0; u < LC; ++u) {
@@ -270,7 +309,7 @@ __global__ __launch_bounds__(256) void k_gather(TxArgs a, const cx<T>* __restric
             uint32_t use;
             if (EVAL) {
 #pragma unroll
-                for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, t.nlat - 1) * a.n + g];
+                for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, t.nlat - 1) * a.rs + g];
                 use = (t.nlat - j0 >= LC) ? (uint32_t)((1ull << LC) - 1) : ((1u << (t.nlat - j0)) - 1u);
             } else {
                 use = unaliased_chunk<LC>(a, t, j0, g, r);
@@ -328,7 +367,7 @@ __global__ __launch_bounds__(256) void k_scatter_eval(TxArgs a, const cx<T>* __r
 #pragma unroll
         for (int q = 0; q < RB; ++q) v[q] = (q < nr) ? coeffs[(rhs0 + q) * a.n + g] : cx<T>{(T)0, (T)0};
         for (int j = 0; j < t.nlat; ++j) {
-            const int64_t r = a.res32[(int64_t)j * a.n + g];
+            const int64_t r = a.res32[(int64_t)j * a.rs + g];
             cx<T>* dst = work + rhs0 * a.work_stride + a.desc[t.lat0 + j].work_off + r;
 #pragma unroll
             for (int q = 0; q < RB; ++q)
@@ -384,7 +423,7 @@ __global__ __launch_bounds__(256) void k_alias_export(TxArgs a, int64_t* res, ui
         int cnt = 0;
         for (int j = 0; j < t.nlat; ++j) {
             const LatDesc D = a.desc[t.lat0 + j];
-            const int64_t r = a.res32[(int64_t)j * a.n + g];
+            const int64_t r = a.res32[(int64_t)j * a.rs + g];
             const bool u = !is_multi(a.bitmaps, D, r);
             cnt += u;
             const int64_t o = (int64_t)j * a.n + g;
@@ -410,7 +449,7 @@ void launch_clear_u32(uint32_t* p, int64_t words, hipStream_t s) {
 
 template <int DP, typename K>
 static void launch_res_narrow(const TxArgs& a, hipStream_t s) {
-    const dim3 grid(grid_for(a.n, 256, 65535));
+    const dim3 grid(grid_for(a.n, 256, 65535), (unsigned)((a.max_nlat + kResLat - 1) / kResLat));
     if (a.ntx == 1) hipLaunchKernelGGL((k_residues_narrow<K, DP, true>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_residues_narrow<K, DP, false>), grid, dim3(256), 0, s, a);
 }
@@ -418,7 +457,10 @@ static void launch_res_narrow(const TxArgs& a, hipStream_t s) {
 template <typename K>
 static void launch_res(const TxArgs& a, hipStream_t s) {
     if (a.narrow) {
-        if (a.zrow == 16) launch_res_narrow<16, K>(a, s);
+        if (a.zpad == 8) launch_res_narrow<8, K>(a, s);
+        else if (a.zpad == 12) launch_res_narrow<12, K>(a, s);
+        else if (a.zpad == 16) launch_res_narrow<16, K>(a, s);
+        else if (a.zpad == 24) launch_res_narrow<24, K>(a, s);
         else launch_res_narrow<32, K>(a, s);
         return;
     }

@@ -215,7 +215,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     std::vector<HistTile> tiles;
     int hist_words = 1;
     {
-        const int rpl = std::max(1, std::min(16, (512 + L - 1) / std::max(1, L)));
+        const int rpl = std::max(1, std::min(16, (256 + L - 1) / std::max(1, L)));
         std::vector<std::vector<HistTile>> byx(L >= 8 ? 8 : 1);
         int txi = 0;
         for (int l = 0; l < L; ++l) {
@@ -234,9 +234,8 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             for (auto& v : byx) tiles.push_back(i < v.size() ? v[i] : HistTile{-1, 0, 0, 0});
     }
     MR1L_HIP_TRY(P->hist.upload(tiles.data(), tiles.size() * sizeof(HistTile)));
-    // fused residue + histogram tiles: each lattice's frequencies split into P_l chunks, each
-    // counted over all bins in LDS; P_l keeps the partial bitmaps (2 words per 32 bins per chunk)
-    // near half the residue bytes while giving chunks of >= 1024 frequencies
+    // fused residue + histogram tiles: each lattice's frequencies split into chunks of one
+    // workgroup iteration, each counted over all bins of the lattice in LDS
     bool fused = L > 0 && n < ((int64_t)1 << 31);   // 32-bit frequency offsets inside the kernel
     int rt_words = 1;
     for (int l = 0; l < L; ++l) fused = fused && P->hdesc[l].bm_words <= kFusedMaxWords;
@@ -249,9 +248,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             LatDesc& D = P->hdesc[l];
             const int64_t fn = P->htx[txi].fn, words = D.bm_words;
             rt_words = std::max<int>(rt_words, (int)words);
-            int64_t pc = std::min<int64_t>((384 + L - 1) / L, std::max<int64_t>(1, fn / (2 * words)));
-            pc = std::max<int64_t>(1, std::min<int64_t>(pc, (fn + 1023) / 1024));
-            const int64_t ch = (fn + pc - 1) / pc;
+            const int64_t ch = (int64_t)kResThreads * res_unroll(P->args.narrow ? P->args.zpad : 0);
             D.rt0 = (int32_t)rtiles.size();
             for (int64_t k0 = 0; k0 < fn; k0 += ch) {
                 rtiles.push_back(ResTile{P->htx[txi].foff + k0, P->htx[txi].foff + std::min(fn, k0 + ch), part_words,
@@ -268,7 +265,8 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         MR1L_HIP_TRY(P->rtiles.upload(rtiles.data(), rtiles.size() * sizeof(ResTile)));
         MR1L_HIP_TRY(P->part.alloc((size_t)std::max<int64_t>(1, part_words) * sizeof(uint32_t)));
     }
-    MR1L_HIP_TRY(P->res32.alloc((size_t)std::max<int64_t>(1, (int64_t)max_nlat * n) * sizeof(int32_t)));
+    const int64_t rstride = (n + 3) / 4 * 4;
+    MR1L_HIP_TRY(P->res32.alloc((size_t)std::max<int64_t>(4, (int64_t)max_nlat * rstride) * sizeof(int32_t)));
     MR1L_HIP_TRY(P->bitmaps.alloc((size_t)std::max<int64_t>(1, P->bm_total) * sizeof(uint32_t)));
     const Plan* sh = sp.share_filters;
     if (sh) {
@@ -304,6 +302,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     a.bitmaps = P->bitmaps.as<uint32_t>();
     a.bm_total = P->bm_total;
     a.res32 = P->res32.as<int32_t>();
+    a.rs = rstride;
     a.hist = P->hist.as<HistTile>();
     a.nhist = (int)tiles.size();
     a.hist_words = hist_words;
