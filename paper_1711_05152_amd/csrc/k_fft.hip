@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
                                                  const cx<T>* __restrict__ filt, int sign,
                                                  const cx<T>* __restrict__ tw) {
     constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
-    constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2;
+    constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
     constexpr int TPL_LG = LGN - kTileLg;
     constexpr int LR0 = stage_lr(LGN2, 0, true), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
     constexpr int NSI = n_stages(LGN2);
@@ -529,28 +529,43 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
     static_assert(stage_lr(LGN2, 0, false) == LRM, "the forward's last and the inverse's first stage must match");
     __shared__ cx<T> lds[Padded<(1 << kTileLg)>::v];
     const int li = blockIdx.x >> TPL_LG;
-    const int r0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGR;
+    const int t = blockIdx.x & ((1 << TPL_LG) - 1);
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
-    cx<T>* w = work + rhs * a.work_stride + D.work_off + ((int64_t)r0 << LGN2);
+    cx<T>* w = work + rhs * a.work_stride + D.work_off;
+    // Rows of the tile: ROWS/2 mirror pairs (p, N1 - p) of the [k1][k2] layout, pair 0 being
+    // (0, N1/2).  The filter spectrum is even (B[k] = B[N - k]), i.e. B[k1][k2] = B[N1-k1][N2-1-k2]
+    // for 0 < k1 < N1, so the second row of a pair reads its partner's filter values (the same
+    // lines, reversed) and the tile fetches half of the filter bytes.
+    constexpr int H = ROWS > 1 ? ROWS / 2 : 1;
+    auto prow = [&](int b) -> int {
+        if constexpr (ROWS == 1) return t;
+        const int p = t * H + (b & (H - 1));
+        return b < H ? p : (p == 0 ? N1 / 2 : N1 - p);
+    };
     cx<T> v[kVals];
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int b, j;
         bfly<LGNB0, ROWS, false>(u, b, j);
+        const cx<T>* src = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
-        for (int r = 0; r < R0; ++r) v[u * R0 + r] = w[(b << LGN2) + j + (r << LGNB0)];
+        for (int r = 0; r < R0; ++r) v[u * R0 + r] = src[j + (r << LGNB0)];
     }
     fft_regs<T, LGN2, ROWS, N2, -1, true, false, false>(lds, v, tw);
     if constexpr (CONV) {
-        const cx<T>* f = filt + D.filt_off + ((int64_t)r0 << LGN2);
+        const cx<T>* f = filt + D.filt_off;
 #pragma unroll
         for (int u = 0; u < kVals / RM; ++u) {
             int b, j;
             bfly<LGNBM, ROWS, false>(u, b, j);
+            const int p = t * H + (b & (H - 1));
+            const bool mirror = ROWS > 1 && b >= H && p != 0;
+            const cx<T>* fr = f + ((int64_t)(mirror ? p : prow(b)) << LGN2);
 #pragma unroll
             for (int r = 0; r < RM; ++r) {
-                const cx<T> fv = f[(b << LGN2) + j + (r << LGNBM)];
+                const int c = j + (r << LGNBM);
+                const cx<T> fv = fr[mirror ? N2 - 1 - c : c];
                 v[u * RM + r] = sign < 0 ? cmul(v[u * RM + r], fv) : cmulc(v[u * RM + r], fv);
             }
         }
@@ -559,16 +574,18 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
         for (int u = 0; u < kVals / RL; ++u) {
             int b, j;
             bfly<LGNBL, ROWS, false>(u, b, j);
+            cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
-            for (int r = 0; r < RL; ++r) w[(b << LGN2) + j + (r << LGNBL)] = v[u * RL + r];
+            for (int r = 0; r < RL; ++r) dstp[j + (r << LGNBL)] = v[u * RL + r];
         }
     } else {
 #pragma unroll
         for (int u = 0; u < kVals / RM; ++u) {
             int b, j;
             bfly<LGNBM, ROWS, false>(u, b, j);
+            cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
-            for (int r = 0; r < RM; ++r) w[(b << LGN2) + j + (r << LGNBM)] = v[u * RM + r];
+            for (int r = 0; r < RM; ++r) dstp[j + (r << LGNBM)] = v[u * RM + r];
         }
     }
 }
