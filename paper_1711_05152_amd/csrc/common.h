@@ -49,6 +49,8 @@ struct LatDesc {
     int32_t small;     // 1: the whole Bluestein convolution runs in one workgroup
     int32_t rt0;       // fused residue/histogram pass: first ResTile of this lattice
     int32_t rtn;       //   and their number
+    int32_t tx;        // transform the lattice belongs to
+    int32_t pad_;
 };
 
 // One entry per independent transform of a plan (a plain plan has one; a batched plan many).
@@ -148,6 +150,16 @@ struct TxArgs {
     int nrt;
     int rt_words;             // largest bm_words over the lattices (LDS per bitmap)
     uint32_t* part;           // partial bitmaps of every ResTile
+    // Fourier-matrix adjoint by counting sort (bsort): per bin (lattice-major like the samples)
+    // the number of frequencies it receives (zero between calls), chunk-local exclusive scans and
+    // chunk bases of the concatenated counts, and per lattice slot the frequencies ordered by bin
+    bool bsort;
+    int32_t* bcnt;            // [sum_M]
+    int32_t* bloc;            // [sum_M]
+    int32_t* bbase;           // [ceil(sum_M / kScanChunk)]
+    int32_t* perm;            // [max_nlat][rs]
+    int64_t nbins;            // sum_M
+    int64_t max_M;            // largest lattice size
     bool fast_mod;            // residues may use the fp64 quotient estimate
     // 32-bit residue path: |k . z| < 2^31 for every frequency and lattice, |k_c| < 2^23 and d <= 32;
     // z32 holds the reduced generators as int32 rows padded with zeros
@@ -169,6 +181,12 @@ template <typename T>
 void launch_clear_bins(const TxArgs& a, cx<T>* work, hipStream_t s);   // Fourier-matrix adjoint only
 template <typename T>
 void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval, hipStream_t s);
+constexpr int kScanChunk = 8192;   // bins per workgroup of the counting-sort scan
+// counting sort of every (frequency, lattice) pair by bin (needs the residues); then, per rhs
+// chunk, bins[m] = sum of c_k over the frequencies in bin m (Fourier-matrix adjoint, no atomics)
+void launch_bin_sort(const TxArgs& a, hipStream_t s);
+template <typename T>
+void launch_bin_sum(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, hipStream_t s);
 void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s);
 
 // Bluestein stages for one group of lattices.  sign = -1: DFT with e^{-2 pi i jm/M} (forward),

@@ -417,6 +417,135 @@ __global__ __launch_bounds__(256) void k_scatter(TxArgs a, const cx<T>* __restri
     }
 }
 
+// ---- Fourier-matrix adjoint by counting sort --------------------------------------------------------
+// bins_l[m] = sum over k with r_l(k) = m of c_k (synthesis A c on the lattices, Sec. 2.1): the pairs
+// (k, l) are counted per bin, the counts scanned, the pairs placed in bin order, and one thread per
+// bin adds its frequencies' coefficients in ascending k (sorted when the bin holds <= kBinSort of
+// them), so every bin is written exactly once and the result does not depend on scheduling.
+constexpr int kBinSort = 16;
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void k_bin_count(TxArgs a) {
+    const int j = blockIdx.y;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        if (j >= t.nlat) continue;
+        const int32_t r = a.res32[(int64_t)j * a.rs + g];
+        atomicAdd(&a.bcnt[a.desc[t.lat0 + j].samp_off + r], 1);
+    }
+}
+
+// exclusive scan of 1024 values held one per thread (64-wide waves, then across the 16 waves)
+__device__ __forceinline__ int block_excl_scan_1024(int v, int* lds16, int& total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds16[wv] = x;
+    __syncthreads();
+    int wbase = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        const int ws = lds16[w];
+        if (w < wv) wbase += ws;
+        tot += ws;
+    }
+    __syncthreads();
+    total = tot;
+    return wbase + x - v;
+}
+
+// chunk-local exclusive scans of the counts and chunk totals
+__global__ __launch_bounds__(1024) void k_bin_scan(TxArgs a) {
+    __shared__ int wsum[16];
+    const int64_t c0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * (kScanChunk / 1024);
+    int v[kScanChunk / 1024], run = 0;
+#pragma unroll
+    for (int i = 0; i < kScanChunk / 1024; ++i) {
+        v[i] = c0 + i < a.nbins ? a.bcnt[c0 + i] : 0;
+        run += v[i];
+    }
+    int total;
+    int ex = block_excl_scan_1024(run, wsum, total);
+#pragma unroll
+    for (int i = 0; i < kScanChunk / 1024; ++i) {
+        if (c0 + i < a.nbins) a.bloc[c0 + i] = ex;
+        ex += v[i];
+    }
+    if (threadIdx.x == 0) a.bbase[blockIdx.x] = total;
+}
+
+// exclusive scan of the chunk totals in place (one workgroup)
+__global__ __launch_bounds__(1024) void k_bin_scan_bases(TxArgs a, int nchunks) {
+    __shared__ int wsum[16];
+    int carry = 0;
+    for (int c0 = 0; c0 < nchunks; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nchunks ? a.bbase[i] : 0;
+        int total;
+        const int ex = block_excl_scan_1024(v, wsum, total);
+        if (i < nchunks) a.bbase[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__device__ __forceinline__ int bin_offset(const TxArgs& a, int64_t b) {
+    return a.bloc[b] + a.bbase[b / kScanChunk];
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void k_bin_place(TxArgs a) {
+    const int j = blockIdx.y;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        if (j >= t.nlat) continue;
+        const LatDesc& D = a.desc[t.lat0 + j];
+        const int64_t b = D.samp_off + a.res32[(int64_t)j * a.rs + g];
+        const int pos = bin_offset(a, b) - bin_offset(a, D.samp_off) + atomicSub(&a.bcnt[b], 1) - 1;
+        a.perm[(int64_t)j * a.rs + t.foff + pos] = (int32_t)g;
+    }
+}
+
+// one thread per bin m of lattice blockIdx.y, every right-hand side of the chunk
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_sum(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
+    const int l = blockIdx.y;
+    const LatDesc D = a.desc[l];
+    const TxDesc t = a.tx[D.tx];
+    const int j = l - t.lat0;
+    const int base = bin_offset(a, D.samp_off);
+    const int32_t* pm = a.perm + (int64_t)j * a.rs + t.foff;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < D.M; m += (int64_t)gridDim.x * blockDim.x) {
+        const int beg = bin_offset(a, D.samp_off + m) - base;
+        const int end = m + 1 < D.M ? bin_offset(a, D.samp_off + m + 1) - base : (int)t.fn;
+        const int cnt = end - beg;
+        int ks[kBinSort];
+        if (cnt <= kBinSort) {
+            for (int i = 0; i < cnt; ++i) {   // insertion sort: ascending k
+                const int k = pm[beg + i];
+                int q = i;
+                while (q > 0 && ks[q - 1] > k) {
+                    ks[q] = ks[q - 1];
+                    --q;
+                }
+                ks[q] = k;
+            }
+        }
+        for (int64_t rhs = 0; rhs < a.n_rhs; ++rhs) {
+            const cx<T>* cr = coeffs + rhs * a.n;
+            cx<T> acc = {(T)0, (T)0};
+            if (cnt <= kBinSort) {
+                for (int i = 0; i < cnt; ++i) acc = acc + cr[ks[i]];
+            } else {
+                for (int i = beg; i < end; ++i) acc = acc + cr[pm[i]];
+            }
+            work[rhs * a.work_stride + D.work_off + m] = acc;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_alias_export(TxArgs a, int64_t* res, uint8_t* uniq, uint8_t* counter) {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
         const TxDesc t = a.tx[a.ntx == 1 ? 0 : find_tx(a.tx_foff, a.ntx + 1, g)];
@@ -545,6 +674,27 @@ void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval
     if (a.n_rhs == 1) go(std::integral_constant<int, 1>{});
     else go(std::integral_constant<int, kRB>{});
 }
+
+void launch_bin_sort(const TxArgs& a, hipStream_t s) {
+    if (a.n == 0 || a.L == 0 || a.nbins == 0) return;
+    const dim3 grid(grid_for(a.n, 256, 65535), (unsigned)a.max_nlat);
+    if (a.ntx == 1) hipLaunchKernelGGL((k_bin_count<true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_bin_count<false>), grid, dim3(256), 0, s, a);
+    const int nchunks = (int)((a.nbins + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_bin_scan, dim3(nchunks), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_bin_scan_bases, dim3(1), dim3(1024), 0, s, a, nchunks);
+    if (a.ntx == 1) hipLaunchKernelGGL((k_bin_place<true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_bin_place<false>), grid, dim3(256), 0, s, a);
+}
+
+template <typename T>
+void launch_bin_sum(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, hipStream_t s) {
+    if (a.L == 0 || a.n_rhs == 0) return;
+    hipLaunchKernelGGL((k_bin_sum<T>), dim3(grid_for(a.max_M, 256, 65535), (unsigned)a.L), dim3(256), 0, s, a, coeffs,
+                       work);
+}
+template void launch_bin_sum<float>(const TxArgs&, const cx<float>*, cx<float>*, hipStream_t);
+template void launch_bin_sum<double>(const TxArgs&, const cx<double>*, cx<double>*, hipStream_t);
 
 void launch_alias_export(const TxArgs& a, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s) {
     if (a.n == 0) return;

@@ -186,6 +186,8 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         max_nlat = std::max(max_nlat, sp.tx_L[i]);
     }
 
+    for (int i = 0; i < ntx; ++i)
+        for (int l = P->htx[i].lat0; l < P->htx[i].lat0 + P->htx[i].nlat; ++l) P->hdesc[l].tx = i;
     MR1L_HIP_TRY(P->desc.upload(P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
     MR1L_HIP_TRY(P->tx.upload(P->htx.data(), P->htx.size() * sizeof(TxDesc)));
     MR1L_HIP_TRY(P->tx_foff.upload(foff.data(), foff.size() * sizeof(int64_t)));
@@ -286,6 +288,24 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->rhs_chunk = std::max<int64_t>(1, std::min<int64_t>(P->n_rhs, sp.max_work_bytes / per_rhs));
     }
     MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->rhs_chunk) * sizeof(cx<T>)));
+    // Fourier-matrix adjoint by counting sort where the pairs (k, l) are many (below that, a few
+    // atomics per pair are cheaper than the sort's launches)
+    P->args.bsort = sp.weights == MR1L_W_EVAL && (int64_t)n * max_nlat >= ((int64_t)1 << 16) &&
+                    (int64_t)n * max_nlat < ((int64_t)1 << 31) && P->sum_M < ((int64_t)1 << 31);
+    if (P->args.bsort) {
+        const int64_t nchunks = (P->sum_M + kScanChunk - 1) / kScanChunk;
+        MR1L_HIP_TRY(P->bcnt.alloc((size_t)P->sum_M * sizeof(int32_t)));
+        MR1L_HIP_TRY(hipMemset(P->bcnt.p, 0, (size_t)P->sum_M * sizeof(int32_t)));
+        MR1L_HIP_TRY(P->bloc.alloc((size_t)P->sum_M * sizeof(int32_t)));
+        MR1L_HIP_TRY(P->bbase.alloc((size_t)std::max<int64_t>(1, nchunks) * sizeof(int32_t)));
+        MR1L_HIP_TRY(P->perm.alloc((size_t)std::max<int64_t>(4, (int64_t)max_nlat * rstride) * sizeof(int32_t)));
+        P->args.bcnt = P->bcnt.as<int32_t>();
+        P->args.bloc = P->bloc.as<int32_t>();
+        P->args.bbase = P->bbase.as<int32_t>();
+        P->args.perm = P->perm.as<int32_t>();
+    }
+    P->args.nbins = P->sum_M;
+    P->args.max_M = maxM;
 
     TxArgs& a = P->args;
     a.desc = P->desc.as<LatDesc>();
@@ -425,14 +445,24 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
     index_pass(p, eval, tm, s);
+    if (eval && p->args.bsort && !(p->cache_alias && p->sort_valid)) {
+        tm.begin(0);
+        launch_bin_sort(p->args, s);
+        tm.end();
+        p->sort_valid = p->cache_alias;
+    }
     for (int64_t r0 = 0; r0 < p->n_rhs; r0 += p->rhs_chunk) {
         TxArgs a = p->args;
         a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
         const cx<T>* cc = c + r0 * a.n;
         cx<T>* yc = y + r0 * a.samp_stride;
         tm.begin(6);
-        if (eval) launch_clear_bins<T>(a, work, s);
-        launch_scatter<T>(a, cc, work, eval, s);
+        if (eval && a.bsort) {
+            launch_bin_sum<T>(a, cc, work, s);
+        } else {
+            if (eval) launch_clear_bins<T>(a, work, s);
+            launch_scatter<T>(a, cc, work, eval, s);
+        }
         tm.end();
         for (const FftGroup& g : p->groups) {
             if (g.small) {
@@ -639,6 +669,7 @@ mr1l_status mr1l_cache_alias(mr1l_plan_t plan, int enable) {
     Plan* p = (Plan*)plan;
     p->cache_alias = enable != 0;
     p->alias_valid = false;
+    p->sort_valid = false;
     return MR1L_OK;
 }
 

@@ -136,13 +136,14 @@ struct Plan {
     int64_t work_stride = 0;
     int64_t filt_total = 0;
     int64_t bm_total = 0;
-    DevMem freqs, desc, tx, tx_foff, z, z32, bitmaps, filt, work, grp_lat, res32, hist, rtiles, part;
+    DevMem freqs, desc, tx, tx_foff, z, z32, bitmaps, filt, work, grp_lat, res32, hist, rtiles, part, bcnt, bloc, bbase, perm;
     std::vector<FftGroup> groups;   // lattices grouped by Bluestein length
     void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};
     // plan-cached index work: residues and bitmaps valid from an earlier call
     bool cache_alias = false;
     bool alias_valid = false;
+    bool sort_valid = false;           // counting sort of the Fourier-matrix adjoint, same rule
     // per-stage timing
     bool timing = false;
     struct Rec { int stage; hipEvent_t a, b; };

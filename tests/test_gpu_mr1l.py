@@ -207,3 +207,32 @@ def test_cache_alias_matches_recompute(weights):
         assert same_adj()
     cached.cache_alias(False)
     assert same_adj()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_eval_adjoint_counting_sort(dtype):
+    """Fourier-matrix adjoint on plans with many (k, l) pairs (counting-sort path: bins summed in
+    ascending k, no atomics): parity with the oracle, bit-identical repeated calls, and the same
+    results with plan-cached index work."""
+    torch = require_gpu()
+    p = transform_problem(rng_for(320), 12000, 6, 30, 8, 9000, 20000, n_rhs=3)
+    plan = _plan(p, dtype, "eval")
+    c = _to(torch, p.coeffs, dtype)
+    y1 = plan.adjoint(c)
+    y2 = plan.adjoint(c)
+    assert torch.equal(y1, y2)
+    assert_close(y1.cpu().numpy(), O.adjoint(p.freqs, p.M, p.z, p.coeffs, "eval"), dtype, "eval adjoint")
+    plan.cache_alias(True)
+    for _ in range(2):
+        assert torch.equal(plan.adjoint(c), y1)
+
+
+def test_eval_adjoint_crowded_bins():
+    """A lattice with z = 0 puts every frequency into bin 0 (more frequencies per bin than the
+    in-register sort takes): still the oracle's sum."""
+    torch = require_gpu()
+    p = transform_problem(rng_for(321), 20000, 4, 20, 5, 20000, 40000, n_rhs=1)
+    p.z[2] = 0
+    plan = _plan(p, "c128", "eval")
+    y = plan.adjoint(_to(torch, p.coeffs, "c128"))
+    assert_close(y.cpu().numpy(), O.adjoint(p.freqs, p.M, p.z, p.coeffs, "eval"), "c128", "crowded eval adjoint")
