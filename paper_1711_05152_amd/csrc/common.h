@@ -200,8 +200,12 @@ void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src
 template <typename T>
 void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride, bool src_is_samples,
                cx<T>* work, int sign, bool mask_bins, hipStream_t s);
+// rot_in / rot_out: the sample vector whose column rotation the rows carry when loaded (forward,
+// after stage 1 read samples) or must carry when stored (adjoint, before stage 3 writes samples);
+// NULL for none
 template <typename T>
-void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s);
+void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, const cx<T>* rot_in,
+               const cx<T>* rot_out, hipStream_t s);
 template <typename T>
 void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
                int sign, bool scale_by_invM, hipStream_t s);

@@ -163,6 +163,22 @@ __device__ __forceinline__ bool owned_bin(const uint32_t* __restrict__ bm, const
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
 template <int ELEMS> struct Padded { static constexpr int v = ELEMS + (ELEMS >> 3) + 64; };
 
+// Column rotation of the four-step tiles that touch the sample vector.  Lattice offsets in the
+// samples are arbitrary, so a tile's C columns n2 = c0 .. c0+C-1 of a row would straddle 128-byte
+// lines.  Stage 1 (forward) and stage 3 (adjoint) instead take the columns
+// n2 = (c0 + col - rot) mod N2, rot = (sample address of n = 0, in elements) mod AL, whose samples
+// are line-aligned, and the work area holds column n2 at position (n2 + rot) mod N2, so their
+// work-area accesses stay aligned as well; stage 2 undoes (forward) or applies (adjoint) the
+// rotation when it loads or stores a row.  rot_base is the sample pointer in elements mod 1024.
+template <typename T, int LGN>
+struct Rot {
+    static constexpr int LGN1 = split_lgN1(LGN), C = 1 << (kTileLg - LGN1);
+    static constexpr int AL = C < (int)(128 / sizeof(cx<T>)) ? C : (int)(128 / sizeof(cx<T>));
+    __device__ static int of(int rot_base, int64_t rhs, int64_t stride, int64_t samp_off) {
+        return (int)(((int64_t)rot_base + rhs * stride + samp_off) & (AL - 1));
+    }
+};
+
 // ---- in-register DFTs ------------------------------------------------------------------------------
 template <typename T, int SIGN>
 __device__ __forceinline__ cx<T> mul_si(cx<T> a) {  // a * (SIGN i)
@@ -456,7 +472,7 @@ __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __re
 template <typename T, int LGN, int SRC>
 __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict__ lat, const cx<T>* __restrict__ src,
                                                  int64_t src_stride, cx<T>* work, int sign,
-                                                 const cx<T>* __restrict__ tw) {
+                                                 const cx<T>* __restrict__ tw, int rot_base) {
     constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
     constexpr int LGC = kTileLg - LGN1, C = 1 << LGC, N1 = 1 << LGN1;
     constexpr int S = N1 + 1;
@@ -475,14 +491,17 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
     const cx<T>* in = src + rhs * src_stride + (SRC == 0 ? D.samp_off : D.work_off);
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
     const int64_t nvalid = (SRC == 2) ? ((int64_t)1 << LGN) : D.M;
+    const int rot = SRC == 0 ? Rot<T, LGN>::of(rot_base, rhs, src_stride, D.samp_off) : 0;
+    constexpr int N2M = (1 << LGN2) - 1;
     cx<T> v[kVals];
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int col, j;
         bfly<LGNB0, C, true>(u, col, j);
+        const int n2 = (c0 + col - rot) & N2M;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            const int64_t n = ((int64_t)(j + (r << LGNB0)) << LGN2) + c0 + col;
+            const int64_t n = ((int64_t)(j + (r << LGNB0)) << LGN2) + n2;
             cx<T> x = {(T)0, (T)0};
             if (n < nvalid) {
                 x = in[n];
@@ -493,18 +512,18 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
         }
     }
     fft_regs<T, LGN1, C, S, -1, true, true, true>(lds, v, tw);
-    // outputs: column col, k1 = j + r N1/RL; times w_N^{n2 k1}, stored at k1 N2 + n2
+    // outputs: column n2, k1 = j + r N1/RL; times w_N^{n2 k1}, stored at k1 N2 + (n2 + rot) mod N2
 #pragma unroll
     for (int u = 0; u < kVals / RL; ++u) {
         int col, j;
         bfly<LGNBL, C, true>(u, col, j);
-        const int n2 = c0 + col;
+        const int n2 = (c0 + col - rot) & N2M;
         cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
         const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNBL) & ((1 << LGN) - 1)), LGN, ph);
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k1 = j + (r << LGNBL);
-            w[((int64_t)k1 << LGN2) + n2] = cmul(v[u * RL + r], wk);
+            w[((int64_t)k1 << LGN2) + c0 + col] = cmul(v[u * RL + r], wk);
             wk = cmul(wk, ws);
         }
     }
@@ -517,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
 template <typename T, int LGN, bool CONV>
 __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
                                                  const cx<T>* __restrict__ filt, int sign,
-                                                 const cx<T>* __restrict__ tw) {
+                                                 const cx<T>* __restrict__ tw, int rot_in_base, int rot_out_base) {
     constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
     constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
     constexpr int TPL_LG = LGN - kTileLg;
@@ -533,6 +552,9 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
+    // rotation of the rows as stored by stage 1 / as stage 3 reads them (rot_*_base < 0: none)
+    const int rin = rot_in_base < 0 ? 0 : Rot<T, LGN>::of(rot_in_base, rhs, a.samp_stride, D.samp_off);
+    const int rout = rot_out_base < 0 ? 0 : Rot<T, LGN>::of(rot_out_base, rhs, a.samp_stride, D.samp_off);
     // Rows of the tile: ROWS/2 mirror pairs (p, N1 - p) of the [k1][k2] layout, pair 0 being
     // (0, N1/2).  The filter spectrum is even (B[k] = B[N - k]), i.e. B[k1][k2] = B[N1-k1][N2-1-k2]
     // for 0 < k1 < N1, so the second row of a pair reads its partner's filter values (the same
@@ -550,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
         bfly<LGNB0, ROWS, false>(u, b, j);
         const cx<T>* src = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
-        for (int r = 0; r < R0; ++r) v[u * R0 + r] = src[j + (r << LGNB0)];
+        for (int r = 0; r < R0; ++r) v[u * R0 + r] = src[(j + (r << LGNB0) + rin) & (N2 - 1)];
     }
     fft_regs<T, LGN2, ROWS, N2, -1, true, false, false>(lds, v, tw);
     if constexpr (CONV) {
@@ -576,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
             bfly<LGNBL, ROWS, false>(u, b, j);
             cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
-            for (int r = 0; r < RL; ++r) dstp[j + (r << LGNBL)] = v[u * RL + r];
+            for (int r = 0; r < RL; ++r) dstp[(j + (r << LGNBL) + rout) & (N2 - 1)] = v[u * RL + r];
         }
     } else {
 #pragma unroll
@@ -594,7 +616,7 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
 template <typename T, int LGN, bool TO_SAMPLES>
 __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work, cx<T>* dst,
                                                  int64_t dst_stride, int sign, int scale_by_invM,
-                                                 const cx<T>* __restrict__ tw) {
+                                                 const cx<T>* __restrict__ tw, int rot_base) {
     constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
     constexpr int LGC = kTileLg - LGN1, C = 1 << LGC, N1 = 1 << LGN1;
     constexpr int S = N1 + 1;
@@ -611,18 +633,20 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
+    const int rot = TO_SAMPLES ? Rot<T, LGN>::of(rot_base, rhs, dst_stride, D.samp_off) : 0;
+    constexpr int N2M = (1 << LGN2) - 1;
     cx<T> v[kVals];
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int col, j;
         bfly<LGNB0, C, true>(u, col, j);
-        const int n2 = c0 + col;
+        const int n2 = (c0 + col - rot) & N2M;
         cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
         const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNB0) & ((1 << LGN) - 1)), LGN, ph);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k1 = j + (r << LGNB0);
-            v[u * R0 + r] = cmulc(w[((int64_t)k1 << LGN2) + n2], wk);
+            v[u * R0 + r] = cmulc(w[((int64_t)k1 << LGN2) + c0 + col], wk);
             wk = cmul(wk, ws);
         }
     }
@@ -638,7 +662,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int n1 = j + (r << LGNBL);
-            const int64_t n = ((int64_t)n1 << LGN2) + c0 + col;
+            const int64_t n = ((int64_t)n1 << LGN2) + ((c0 + col - rot) & N2M);
             if (n < D.M) out[n] = cscale(cmul(v[u * RL + r], chirp<T>(n, D.M, D.invM, sign, ph)), sc);
         }
     }
@@ -752,6 +776,7 @@ void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src
 template <typename T>
 void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride, bool src_is_samples,
                cx<T>* work, int sign, bool mask_bins, hipStream_t s) {
+    const int rb = (int)(((uintptr_t)src / sizeof(cx<T>)) & 1023);
     if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -760,16 +785,19 @@ void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src
     with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
         constexpr int lg = decltype(LG)::value;
         if (src_is_samples)
-            hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
+            hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw, rb);
         else if (mask_bins)
-            hipLaunchKernelGGL((k_p1<T, lg, 3>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
+            hipLaunchKernelGGL((k_p1<T, lg, 3>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
         else
-            hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw);
+            hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
     });
 }
 
 template <typename T>
-void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, hipStream_t s) {
+void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* filt, int sign, const cx<T>* rot_in,
+               const cx<T>* rot_out, hipStream_t s) {
+    const int ri = rot_in ? (int)(((uintptr_t)rot_in / sizeof(cx<T>)) & 1023) : -1;
+    const int ro = rot_out ? (int)(((uintptr_t)rot_out / sizeof(cx<T>)) & 1023) : -1;
     if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -777,13 +805,14 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
     const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
     with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
         constexpr int lg = decltype(LG)::value;
-        hipLaunchKernelGGL((k_p2<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, filt, sign, tw);
+        hipLaunchKernelGGL((k_p2<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, filt, sign, tw, ri, ro);
     });
 }
 
 template <typename T>
 void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
                int sign, bool scale_by_invM, hipStream_t s) {
+    const int rb = dst_is_samples ? (int)(((uintptr_t)dst / sizeof(cx<T>)) & 1023) : 0;
     if (g.nlat == 0 || a.n_rhs == 0) return;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -793,10 +822,10 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
         constexpr int lg = decltype(LG)::value;
         if (dst_is_samples)
             hipLaunchKernelGGL((k_p3<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, dst, dst_stride, sign,
-                               (int)scale_by_invM, tw);
+                               (int)scale_by_invM, tw, rb);
         else
             hipLaunchKernelGGL((k_p3<T, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, work, dst, dst_stride,
-                               sign, (int)scale_by_invM, tw);
+                               sign, (int)scale_by_invM, tw, 0);
     });
 }
 
@@ -805,7 +834,8 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
                                             const cx<T>*, cx<T>*, int64_t, bool, int, bool, bool, hipStream_t);  \
     template void launch_p1<T>(const TxArgs&, const FftGroup&, const cx<T>*, int64_t, bool, cx<T>*, int, bool,    \
                                hipStream_t);                                                                      \
-    template void launch_p2<T>(const TxArgs&, const FftGroup&, cx<T>*, const cx<T>*, int, hipStream_t);           \
+    template void launch_p2<T>(const TxArgs&, const FftGroup&, cx<T>*, const cx<T>*, int, const cx<T>*,          \
+                               const cx<T>*, hipStream_t);           \
     template void launch_p3<T>(const TxArgs&, const FftGroup&, cx<T>*, cx<T>*, int64_t, bool, int, bool,          \
                                hipStream_t);
 MR1L_INST_FFT(float)
@@ -845,9 +875,9 @@ void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std:
             with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
                 constexpr int lg = decltype(LG)::value;
                 hipLaunchKernelGGL((k_p1<double, lg, 2>), grid, dim3(kThreads), 0, s, a, g.lat,
-                                   (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw);
+                                   (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw, 0);
                 hipLaunchKernelGGL((k_p2<double, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, tmp,
-                                   (const cx<double>*)nullptr, -1, tw);
+                                   (const cx<double>*)nullptr, -1, tw, -1, -1);
             });
         }
     }

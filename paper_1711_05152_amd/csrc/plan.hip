@@ -424,7 +424,7 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
             launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, false, s);
             tm.end();
             tm.begin(3);
-            launch_p2<T>(a, g, work, filt, -1, s);
+            launch_p2<T>(a, g, work, filt, -1, yc, nullptr, s);
             tm.end();
             tm.begin(4);
             launch_p3<T>(a, g, work, work, a.work_stride, false, -1, !eval, s);
@@ -476,7 +476,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
             launch_p1<T>(a, g, work, a.work_stride, false, work, +1, !eval, s);
             tm.end();
             tm.begin(3);
-            launch_p2<T>(a, g, work, filt, +1, s);
+            launch_p2<T>(a, g, work, filt, +1, nullptr, yc, s);
             tm.end();
             tm.begin(4);
             launch_p3<T>(a, g, work, yc, a.samp_stride, true, +1, !eval, s);
