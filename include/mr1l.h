@@ -146,6 +146,9 @@ mr1l_status mr1l_timing_read(mr1l_plan_t plan, double* ms_sum, int64_t* launches
  *   d, n, freqs   host int32 [n][d] frequency set (distinct rows)
  *   c, gamma      oversampling factor c > 1 and failure-probability bound 0 < gamma < 1
  *   b             maximal number of Alg. 1 calls (>= 1); the last call is kept if none covers I
+ *   redraw        0: Alg. 1 as stated.  > 0: the earlier construction Alg. 1 modifies (remark
+ *                 after Alg. 1): while Lambda(z_L, M_L) reconstructs no frequency not yet covered,
+ *                 z_L is drawn again, at most redraw times (stream fields (t, call, L, a))
  *   seed, t       key of the generating-vector stream (SplitMix64, fields (t, call, L))
  *   L_cap         capacity of M and z (L_max = ceil(c^2/(c-1)^2 (ln n - ln gamma)/2) suffices)
  *   L_out         number of lattices returned
@@ -155,7 +158,7 @@ mr1l_status mr1l_timing_read(mr1l_plan_t plan, double* ms_sum, int64_t* launches
  *   device        device the residue/alias passes run on (synchronous)
  * Returns MR1L_WARN_UNCOVERED when b calls did not cover I (outputs still valid). */
 mr1l_status mr1l_construct(int d, int64_t n, const int32_t* freqs, double c, double gamma, int b,
-                           uint64_t seed, int64_t t, int L_cap, int* L_out, int64_t* M,
+                           int redraw, uint64_t seed, int64_t t, int L_cap, int* L_out, int64_t* M,
                            int64_t* z, int* calls, int64_t* n_uncovered, int device);
 
 /* ---- dimension-incremental sparse FFT (Alg. 3) ------------------------------------------------ */
@@ -189,6 +192,13 @@ typedef struct sfft_params {
     int zero_anchors;        /* 1: anchors fixed to 0 (r = 1 mode of Sec. 3.1)   */
     int plain;               /* 1: one transform call per repetition (no batching
                                 of repetitions / 1-D lines as right-hand sides)  */
+    int redraw;              /* construction variant of step 2b (see
+                                mr1l_construct); 0: Alg. 1                       */
+    const int32_t* order;    /* NULL, or host int32 [d]: a permutation; step t
+                                works on component order[t-1] (any component
+                                order may be used).  Stream keys follow the step;
+                                output rows hold the original components, listed
+                                lexicographically in the processing order        */
 } sfft_params;
 
 #define SFFT_MAX_D 64
@@ -200,6 +210,7 @@ typedef struct sfft_stats {
     int32_t L[SFFT_MAX_D];         /* lattices used at step t                          */
     int64_t sumM[SFFT_MAX_D];      /* sum of their sizes                               */
     int32_t calls[SFFT_MAX_D];     /* Alg. 1 calls at step t                           */
+    int32_t redraws[SFFT_MAX_D];   /* generating vectors drawn again (redraw variant)  */
     int64_t uncovered[SFFT_MAX_D]; /* frequencies of J_t in no I_l after the last call */
     int64_t samples;               /* distinct nodes: sum r K_t + sum r~ (1 - L + sum M) */
     int64_t samples_full;          /* values drawn (every lattice sampled in full)     */

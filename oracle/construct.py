@@ -15,6 +15,13 @@ reconstructing, at most b calls in total (reading R3 of "up to b-1 times"); if n
 calls covers I the last one is kept (reading R4) and the uncovered frequencies have counter 0.
 
 The generating vectors come from the Z stream of ``oracle.rng`` keyed by (t, attempt, L).
+
+Variant (``redraw`` > 0): the earlier construction that Alg. 1 modifies (remark after Alg. 1)
+checks, after drawing z_L, whether Lambda(z_L, M_L) reconstructs a frequency of I not yet in I~;
+if not, z_L is drawn again (ZREDRAW stream, redraw a = 1, 2, ...) and the lattice is kept only
+once it adds a frequency.  Reading: at most ``redraw`` redraws per lattice, after which the last
+draw is kept (the unbounded loop of the original could run forever when no generating vector
+separates a remaining frequency).
 """
 from __future__ import annotations
 
@@ -75,9 +82,19 @@ def prime_sizes(freqs: np.ndarray, lam_value: float, count: int) -> list[int]:
     return out
 
 
+def _draw_z(k: int, d: int, M: int) -> list[int]:
+    ctr = 0
+    z = []
+    for _ in range(d):
+        v, ctr = R.uniform_int(k, ctr, M)
+        z.append(v)
+    return z
+
+
 def construct(freqs, c: float = 2.0, gamma: float = 0.5, seed: int = 0, t: int = 0,
-              attempt: int = 0):
-    """One call of Alg. 1.  Returns (M [L], z [L, d], covered)."""
+              attempt: int = 0, redraw: int = 0, stats: dict | None = None):
+    """One call of Alg. 1 (``redraw`` > 0: the redraw variant of the module docstring).
+    Returns (M [L], z [L, d], covered); ``stats['redraws']`` counts the redraws."""
     freqs = np.asarray(freqs, dtype=np.int64)
     n, d = freqs.shape
     if n == 0:
@@ -89,27 +106,30 @@ def construct(freqs, c: float = 2.0, gamma: float = 0.5, seed: int = 0, t: int =
     covered = np.zeros(n, bool)
     for L in range(1, L_max + 1):
         M_L = primes[L - 1]
-        k = R.key(seed, R.Z, t, attempt, L)
-        ctr = 0
-        z_L = []
-        for _ in range(d):
-            v, ctr = R.uniform_int(k, ctr, M_L)
-            z_L.append(v)
+        z_L = _draw_z(R.key(seed, R.Z, t, attempt, L), d, M_L)
+        _, uniq, _ = unaliased_sets(freqs, [M_L], [z_L])
+        a = 0
+        while redraw > 0 and a < redraw and not (uniq[0] & ~covered).any():
+            a += 1
+            z_L = _draw_z(R.key(seed, R.ZREDRAW, t, attempt, L, a), d, M_L)
+            _, uniq, _ = unaliased_sets(freqs, [M_L], [z_L])
+        if stats is not None:
+            stats["redraws"] = stats.get("redraws", 0) + a
         Ms.append(M_L)
         zs.append(z_L)
-        _, uniq, _ = unaliased_sets(freqs, [M_L], [z_L])
         covered |= uniq[0]
         if covered.all():
             break
     return np.array(Ms, np.int64), np.array(zs, np.int64).reshape(len(Ms), d), bool(covered.all())
 
 
-def construct_retry(freqs, b: int, c: float = 2.0, gamma: float = 0.5, seed: int = 0, t: int = 0):
+def construct_retry(freqs, b: int, c: float = 2.0, gamma: float = 0.5, seed: int = 0, t: int = 0,
+                    redraw: int = 0, stats: dict | None = None):
     """Alg. 1 called until reconstructing, at most b calls (Alg. 3 step 2b).
     Returns (M, z, covered, calls)."""
     result = None
     for attempt in range(max(1, b)):
-        result = construct(freqs, c, gamma, seed, t, attempt)
+        result = construct(freqs, c, gamma, seed, t, attempt, redraw, stats)
         if result[2]:
             return result + (attempt + 1,)
     return result + (max(1, b),)

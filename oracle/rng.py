@@ -25,6 +25,10 @@ Streams (purpose tag, then fields):
                  samples, kind 1: lattice samples): Box-Muller from u1 = uniform01(key, 2g),
                  u2 = uniform01(key, 2g+1): eta = sigma/sqrt(2) * sqrt(-2 ln(1-u1)) *
                  (cos 2 pi u2 + i sin 2 pi u2)   (noise model of Sec. 5.2).
+  ZREDRAW  = 5 : (t, attempt, L, a)  a-th redraw (a >= 1) of the generating vector of lattice L
+                 in the construction variant that redraws z_L until the lattice reconstructs a
+                 frequency not yet covered (the earlier construction the paper compares Alg. 1
+                 with); a = 0 is the Z stream.
 """
 from __future__ import annotations
 
@@ -35,7 +39,7 @@ GAMMA = 0x9E3779B97F4A7C15
 C1 = 0xBF58476D1CE4E5B9
 C2 = 0x94D049BB133111EB
 
-Z, ANCHOR1D, ANCHOR, NOISE = 1, 2, 3, 4
+Z, ANCHOR1D, ANCHOR, NOISE, ZREDRAW = 1, 2, 3, 4, 5
 
 
 def mix64(x: int) -> int:

@@ -24,6 +24,13 @@ candidate list, keep the first s.  Sets are kept lexicographically sorted (readi
 Empty I^(t) or J_t ends the run with the empty set (reading R14).  For d = 1 the output is
 I^(1) with the coefficients of the last repetition.
 
+Component order (the remark that any permutation of the components may be used): with
+``order`` = (pi_1, .., pi_d), step t works on component pi_t, i.e. the run above on the search
+space and black box with their components permuted; every random stream is keyed by the step t.
+The output frequencies are returned in the original components, in the lexicographic order of
+the processing order (reading R20).  ``redraw`` selects the construction variant of
+``oracle.construct`` for step 2b.
+
 The black box is a planted sparse polynomial; its samples on a lattice come either from direct
 evaluation at explicit nodes (tier 0) or from the identity
   p(j z/M mod 1, x~) = sum_h [c_h e^{2 pi i h_{t+1..d} . x~}] e^{2 pi i j (h_{1..t} . z mod M)/M}
@@ -76,6 +83,10 @@ class PlantedBlackBox:
             ph = nodes[a:a + 4096] @ self.freqs.T.astype(np.float64)
             out[a:a + 4096] = np.exp(2j * np.pi * ph) @ self.coeffs
         return out
+
+    def permuted(self, order) -> "PlantedBlackBox":
+        """The same polynomial with its components in the processing order ``order``."""
+        return PlantedBlackBox(self.freqs[:, np.asarray(order)], self.coeffs, self.sigma, self.noise_seed)
 
     def _noise(self, kind, t, i, count):
         if self.sigma == 0.0:
@@ -136,10 +147,21 @@ class SfftResult:
 
 
 def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = None,
-         r: int = 1, b: int = 10, seed: int = 0, tier: int = 1, zero_anchors: bool = False) -> SfftResult:
+         r: int = 1, b: int = 10, seed: int = 0, tier: int = 1, zero_anchors: bool = False,
+         redraw: int = 0, order=None) -> SfftResult:
     """Alg. 3 on the box search space [box_lo, box_hi] (inclusive, per component).
     ``zero_anchors``: anchor components fixed to 0 instead of drawn (the r = 1 setting of the
-    remark on coefficients with a common sign of real or imaginary part, Sec. 3.1)."""
+    remark on coefficients with a common sign of real or imaginary part, Sec. 3.1).
+    ``redraw``: construction variant (see ``oracle.construct``); ``order``: component order."""
+    if order is not None and list(order) != list(range(len(box_lo))):
+        order = np.asarray(order, np.int64)
+        assert sorted(order.tolist()) == list(range(len(box_lo))), "order must be a permutation"
+        res = sfft(np.asarray(box_lo)[order], np.asarray(box_hi)[order], black_box.permuted(order), delta, s,
+                   s_local, r, b, seed, tier, zero_anchors, redraw, None)
+        orig = np.empty_like(res.freqs)
+        orig[:, order] = res.freqs
+        res.freqs = orig
+        return res
     lo = np.asarray(box_lo, np.int64)
     hi = np.asarray(box_hi, np.int64)
     d = len(lo)
@@ -179,7 +201,8 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
             return res
         J = np.concatenate([np.repeat(prev, len(It), axis=0),
                             np.tile(It, prev.shape[0]).reshape(-1, 1)], axis=1)
-        M, z, covered, calls = construct_retry(J, b, seed=seed, t=t)
+        cstats: dict = {}
+        M, z, covered, calls = construct_retry(J, b, seed=seed, t=t, redraw=redraw, stats=cstats)
         r_t, s_t = (r, s_local) if t < d else (1, s)
         flags = np.zeros(J.shape[0], bool)
         for i in range(1, r_t + 1):
@@ -192,7 +215,7 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
             res.samples += 1 - len(M) + int(np.sum(M))
             res.samples_full += int(np.sum(M))
         res.steps.append(dict(t=t, n_It=len(It), n_J=J.shape[0], L=len(M), sumM=int(np.sum(M)),
-                              calls=calls, covered=covered, M=M, z=z))
+                              calls=calls, covered=covered, M=M, z=z, redraws=cstats.get("redraws", 0)))
         prev = J[flags]
     res.freqs = prev.astype(np.int32)
     res.coeffs = last_coeffs[flags]

@@ -37,7 +37,8 @@ class SfftPlanted(C.Structure):
 class SfftParams(C.Structure):
     _fields_ = [("delta", C.c_double), ("s", C.c_int64), ("s_local", C.c_int64), ("r", C.c_int),
                 ("b", C.c_int), ("seed", C.c_uint64), ("dtype", C.c_int), ("c", C.c_double),
-                ("gamma", C.c_double), ("zero_anchors", C.c_int), ("plain", C.c_int)]
+                ("gamma", C.c_double), ("zero_anchors", C.c_int), ("plain", C.c_int), ("redraw", C.c_int),
+                ("order", C.c_void_p)]
 
 
 SFFT_MAX_D = 64
@@ -47,6 +48,7 @@ class SfftStats(C.Structure):
     _fields_ = [("d", C.c_int), ("n_It", C.c_int64 * SFFT_MAX_D), ("n_J", C.c_int64 * SFFT_MAX_D),
                 ("n_detected", C.c_int64 * SFFT_MAX_D), ("L", C.c_int32 * SFFT_MAX_D),
                 ("sumM", C.c_int64 * SFFT_MAX_D), ("calls", C.c_int32 * SFFT_MAX_D),
+                ("redraws", C.c_int32 * SFFT_MAX_D),
                 ("uncovered", C.c_int64 * SFFT_MAX_D), ("samples", C.c_int64),
                 ("samples_full", C.c_int64), ("ms_sampling", C.c_double), ("ms_transform", C.c_double),
                 ("ms_construct", C.c_double), ("ms_select", C.c_double), ("ms_total", C.c_double)]
@@ -75,7 +77,7 @@ def lib() -> C.CDLL:
         "mr1l_timing_enable": [vp, i32],
         "mr1l_cache_alias": [vp, i32],
         "mr1l_timing_read": [vp, vp, vp, vp],
-        "mr1l_construct": [i32, i64, vp, dbl, dbl, i32, u64, i64, i32, C.POINTER(i32), vp, vp,
+        "mr1l_construct": [i32, i64, vp, dbl, dbl, i32, i32, u64, i64, i32, C.POINTER(i32), vp, vp,
                            C.POINTER(i32), C.POINTER(i64), i32],
         "sfft_detect": [i32, vp, vp, SAMPLER_FN, vp, C.POINTER(SfftPlanted), C.POINTER(SfftParams), i64,
                         C.POINTER(i64), vp, vp, C.POINTER(SfftStats), i32],

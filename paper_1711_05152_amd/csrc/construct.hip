@@ -111,11 +111,13 @@ static mr1l_status congruent_pair_exists(const void* f, int64_t nf, int d, int64
 
 template <typename K>
 static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, int64_t expansion, double c,
-                               double gamma, int b, uint64_t seed, int64_t t, hipStream_t s, ConstructResult* out) {
+                               double gamma, int b, int redraw, uint64_t seed, int64_t t, hipStream_t s,
+                               ConstructResult* out) {
     out->M.clear();
     out->z.clear();
     out->calls = 0;
     out->uncovered = 0;
+    out->redraws = 0;
     if (n == 0) return MR1L_OK;
     const int64_t L_max = lmax_rule(n, c, gamma);
     const double lambda = c * (double)(n - 1);
@@ -169,23 +171,32 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
         unsigned long long ncov = 0;
         for (int64_t L = 1; L <= L_max; ++L) {
             const int64_t M = primes[L - 1];
-            const uint64_t key = Rng::key(seed, {Rng::Z, t, call, L});
-            uint64_t ctr = 0;
-            for (int i = 0; i < d; ++i) zl[i] = (int64_t)Rng::uniform_int(key, &ctr, (uint64_t)M);
+            const unsigned long long before = ncov;
+            for (int a = 0;; ++a) {
+                // draw a = 0: the Z stream of Alg. 1; a >= 1: redraws of the variant
+                const uint64_t key = a == 0 ? Rng::key(seed, {Rng::Z, t, call, L})
+                                            : Rng::key(seed, {Rng::ZREDRAW, t, call, L, a});
+                uint64_t ctr = 0;
+                for (int i = 0; i < d; ++i) zl[i] = (int64_t)Rng::uniform_int(key, &ctr, (uint64_t)M);
+                const int64_t w = (M + 31) / 32;
+                MR1L_HIP_TRY(hipMemcpyAsync(zdev.p, zl.data(), d * sizeof(int64_t), hipMemcpyHostToDevice, s));
+                MR1L_HIP_TRY(hipMemsetAsync(bm.p, 0, 2 * w * sizeof(uint32_t), s));
+                MR1L_HIP_TRY(hipMemsetAsync(count.p, 0, sizeof(unsigned long long), s));
+                hipLaunchKernelGGL(k_trial_hist<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
+                                   zdev.as<int64_t>(), M, 1.0 / (double)M, fast, bm.as<uint32_t>(), w);
+                // covered only grows by this lattice's unaliased frequencies; a lattice that adds
+                // none leaves it unchanged, so a rejected draw needs no undo
+                hipLaunchKernelGGL(k_trial_cover<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
+                                   zdev.as<int64_t>(), M, 1.0 / (double)M, fast, (const uint32_t*)bm.p, w,
+                                   covered.as<uint8_t>(), count.as<unsigned long long>());
+                MR1L_HIP_TRY(hipGetLastError());
+                MR1L_HIP_TRY(hipMemcpyAsync(&ncov, count.p, sizeof(ncov), hipMemcpyDeviceToHost, s));
+                MR1L_HIP_TRY(hipStreamSynchronize(s));
+                if (ncov > before || a >= redraw) break;
+                ++out->redraws;
+            }
             out->M.push_back(M);
             out->z.insert(out->z.end(), zl.begin(), zl.end());
-            const int64_t w = (M + 31) / 32;
-            MR1L_HIP_TRY(hipMemcpyAsync(zdev.p, zl.data(), d * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            MR1L_HIP_TRY(hipMemsetAsync(bm.p, 0, 2 * w * sizeof(uint32_t), s));
-            MR1L_HIP_TRY(hipMemsetAsync(count.p, 0, sizeof(unsigned long long), s));
-            hipLaunchKernelGGL(k_trial_hist<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
-                               zdev.as<int64_t>(), M, 1.0 / (double)M, fast, bm.as<uint32_t>(), w);
-            hipLaunchKernelGGL(k_trial_cover<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
-                               zdev.as<int64_t>(), M, 1.0 / (double)M, fast, (const uint32_t*)bm.p, w,
-                               covered.as<uint8_t>(), count.as<unsigned long long>());
-            MR1L_HIP_TRY(hipGetLastError());
-            MR1L_HIP_TRY(hipMemcpyAsync(&ncov, count.p, sizeof(ncov), hipMemcpyDeviceToHost, s));
-            MR1L_HIP_TRY(hipStreamSynchronize(s));
             if ((int64_t)ncov == n) break;
         }
         out->uncovered = n - (int64_t)ncov;
@@ -195,8 +206,8 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
 }
 
 mr1l_status construct_lattices(int d, int64_t n, const int32_t* host_freqs, const void* dev_freqs, int ktype,
-                               int64_t maxabs, int64_t expansion, double c, double gamma, int b, uint64_t seed,
-                               int64_t t, int device, hipStream_t s, ConstructResult* out) {
+                               int64_t maxabs, int64_t expansion, double c, double gamma, int b, int redraw,
+                               uint64_t seed, int64_t t, int device, hipStream_t s, ConstructResult* out) {
     MR1L_HIP_TRY(hipSetDevice(device));
     DevMem packed;
     const void* f = dev_freqs;
@@ -221,9 +232,9 @@ mr1l_status construct_lattices(int d, int64_t n, const int32_t* host_freqs, cons
         f = packed.p;
     }
     switch (ktype) {
-        case K_I8: return construct_t<int8_t>(d, n, f, maxabs, expansion, c, gamma, b, seed, t, s, out);
-        case K_I16: return construct_t<int16_t>(d, n, f, maxabs, expansion, c, gamma, b, seed, t, s, out);
-        default: return construct_t<int32_t>(d, n, f, maxabs, expansion, c, gamma, b, seed, t, s, out);
+        case K_I8: return construct_t<int8_t>(d, n, f, maxabs, expansion, c, gamma, b, redraw, seed, t, s, out);
+        case K_I16: return construct_t<int16_t>(d, n, f, maxabs, expansion, c, gamma, b, redraw, seed, t, s, out);
+        default: return construct_t<int32_t>(d, n, f, maxabs, expansion, c, gamma, b, redraw, seed, t, s, out);
     }
 }
 
@@ -232,18 +243,18 @@ mr1l_status construct_lattices(int d, int64_t n, const int32_t* host_freqs, cons
 using namespace mr1l;
 
 extern "C" mr1l_status mr1l_construct(int d, int64_t n, const int32_t* freqs, double c, double gamma, int b,
-                                      uint64_t seed, int64_t t, int L_cap, int* L_out, int64_t* M, int64_t* z,
-                                      int* calls, int64_t* n_uncovered, int device) {
+                                      int redraw, uint64_t seed, int64_t t, int L_cap, int* L_out, int64_t* M,
+                                      int64_t* z, int* calls, int64_t* n_uncovered, int device) {
     try {
         clear_error();
         if (d < 1 || d > 64 || n < 0 || (n > 0 && !freqs) || !(c > 1.0) || !(gamma > 0.0 && gamma < 1.0) || b < 1 ||
-            !L_out || L_cap < 0 || (L_cap > 0 && (!M || !z))) {
+            redraw < 0 || !L_out || L_cap < 0 || (L_cap > 0 && (!M || !z))) {
             set_error("invalid argument to mr1l_construct");
             return MR1L_ERR_ARG;
         }
         ConstructResult r;
-        mr1l_status st = construct_lattices(d, n, freqs, nullptr, K_I32, 0, 0, c, gamma, b, seed, t, device,
-                                            nullptr, &r);
+        mr1l_status st = construct_lattices(d, n, freqs, nullptr, K_I32, 0, 0, c, gamma, b, redraw, seed, t,
+                                            device, nullptr, &r);
         if (st != MR1L_OK) return st;
         const int L = (int)r.M.size();
         *L_out = L;

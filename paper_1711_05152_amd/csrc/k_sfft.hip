@@ -105,28 +105,34 @@ __global__ void k_add_noise(cx<T>* y, int64_t len, const uint64_t* __restrict__ 
 
 // ---- explicit nodes for a caller-supplied black box -------------------------------------------------
 // lattice nodes (j z_l mod M_l)/M_l in components < t, anchors in components >= t
+// col: NULL, or the column of the node array that holds processing component k (component
+// order of the caller's black box)
 __global__ void k_nodes_lattice(const int64_t* __restrict__ M, const int64_t* __restrict__ off, const int64_t* __restrict__ z,
-                                int L, int t, int d, const double* __restrict__ anchors, double* nodes) {
+                                int L, int t, int d, const double* __restrict__ anchors, double* nodes,
+                                const int* __restrict__ col) {
     const int l = blockIdx.y;
     const int64_t Ml = M[l];
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < Ml; j += (int64_t)gridDim.x * blockDim.x) {
         double* x = nodes + (off[l] + j) * d;
         for (int k = 0; k < d; ++k) {
+            double v;
             if (k < t) {
-                const int64_t v = (j * z[(int64_t)l * t + k]) % Ml;   // j, z < M < 2^23
-                x[k] = (double)v / (double)Ml;
+                const int64_t q = (j * z[(int64_t)l * t + k]) % Ml;   // j, z < M < 2^23
+                v = (double)q / (double)Ml;
             } else {
-                x[k] = anchors[k];
+                v = anchors[k];
             }
+            x[col ? col[k] : k] = v;
         }
     }
 }
 
 // 1-D line: anchors everywhere, component tc = l / K
-__global__ void k_nodes_1d(int64_t K, int tc, int d, const double* __restrict__ anchors, double* nodes) {
+__global__ void k_nodes_1d(int64_t K, int tc, int d, const double* __restrict__ anchors, double* nodes,
+                           const int* __restrict__ col) {
     const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (l >= K) return;
-    for (int k = 0; k < d; ++k) nodes[l * d + k] = (k == tc) ? (double)l / (double)K : anchors[k];
+    for (int k = 0; k < d; ++k) nodes[l * d + (col ? col[k] : k)] = (k == tc) ? (double)l / (double)K : anchors[k];
 }
 
 // ---- selection -------------------------------------------------------------------------------------
@@ -339,12 +345,12 @@ void sf_add_noise(int dt, void* y, int64_t len, int nrep, const uint64_t* keys, 
 }
 
 void sf_nodes_lattice(const int64_t* M, const int64_t* off, const int64_t* z, int L, int64_t maxM, int t, int d,
-                      const double* anchors, double* nodes, hipStream_t st) {
-    hipLaunchKernelGGL(k_nodes_lattice, g1(maxM, L), dim3(256), 0, st, M, off, z, L, t, d, anchors, nodes);
+                      const double* anchors, double* nodes, const int* col, hipStream_t st) {
+    hipLaunchKernelGGL(k_nodes_lattice, g1(maxM, L), dim3(256), 0, st, M, off, z, L, t, d, anchors, nodes, col);
 }
 
-void sf_nodes_1d(int64_t K, int tc, int d, const double* anchors, double* nodes, hipStream_t st) {
-    hipLaunchKernelGGL(k_nodes_1d, g1(K), dim3(256), 0, st, K, tc, d, anchors, nodes);
+void sf_nodes_1d(int64_t K, int tc, int d, const double* anchors, double* nodes, const int* col, hipStream_t st) {
+    hipLaunchKernelGGL(k_nodes_1d, g1(K), dim3(256), 0, st, K, tc, d, anchors, nodes, col);
 }
 
 void sf_select(int dt, const void* coeffs, int64_t n, int64_t n_rhs, double delta, int64_t s, uint8_t* flags,

@@ -93,7 +93,7 @@ struct Rng {
             if (u >= floor_reject) return u % M;
         }
     }
-    enum Purpose : int64_t { Z = 1, ANCHOR1D = 2, ANCHOR = 3, NOISE = 4 };
+    enum Purpose : int64_t { Z = 1, ANCHOR1D = 2, ANCHOR = 3, NOISE = 4, ZREDRAW = 5 };
 };
 
 // Description of the transforms a plan holds.  A plain plan has one transform; a batched plan
@@ -160,13 +160,16 @@ mr1l_status plan_adjoint(Plan* p, const void* coeffs, void* samples, hipStream_t
 mr1l_status plan_alias(Plan* p, int64_t* res, uint8_t* uniq, uint8_t* counter, hipStream_t s);
 
 // Alg. 1 (+ repetition, Alg. 3 step 2b) on device-resident or host frequencies.
+// redraw > 0: the construction variant that draws z_L again (at most redraw times) while the
+// lattice reconstructs no frequency not yet covered
 struct ConstructResult {
     std::vector<int64_t> M, z;
     int calls = 0;
     int64_t uncovered = 0;
+    int64_t redraws = 0;
 };
 mr1l_status construct_lattices(int d, int64_t n, const int32_t* host_freqs, const void* dev_freqs, int ktype,
-                               int64_t maxabs, int64_t expansion, double c, double gamma, int b, uint64_t seed,
-                               int64_t t, int device, hipStream_t s, ConstructResult* out);
+                               int64_t maxabs, int64_t expansion, double c, double gamma, int b, int redraw,
+                               uint64_t seed, int64_t t, int device, hipStream_t s, ConstructResult* out);
 
 }  // namespace mr1l

@@ -59,6 +59,11 @@ struct Ctx {
     DevMem hc;              // complex double [s]
     int64_t s_pl = 0;
     int64_t pl_maxabs = 0;
+    // component order: step t works on component order[t]; the box and the planted frequencies
+    // are held in processing order, caller nodes are written in the caller's columns
+    std::vector<int> order;
+    std::vector<int32_t> plo, phi;
+    DevMem dcol;
 };
 
 mr1l_status sync_check(hipStream_t st) {
@@ -139,7 +144,8 @@ mr1l_status detect_1d(Ctx& C, std::vector<DevMem>& It, std::vector<int64_t>& nIt
             DevMem nodes;
             MR1L_HIP_TRY(nodes.alloc((size_t)K * d * sizeof(double)));
             for (int q = 0; q < njobs; ++q) {
-                sf_nodes_1d(K, comp[q], d, dA.as<double>() + (size_t)q * d, nodes.as<double>(), C.st);
+                sf_nodes_1d(K, comp[q], d, dA.as<double>() + (size_t)q * d, nodes.as<double>(),
+                            C.dcol.p ? C.dcol.as<int>() : nullptr, C.st);
                 if (C.sampler(C.user, d, K, nodes.as<double>(), (char*)y.p + (size_t)q * K * csz, C.st) != 0) {
                     set_error("sampler callback returned an error");
                     return MR1L_ERR_CALLBACK;
@@ -240,7 +246,8 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
         for (int c = 0; c < t; ++c) expansion = std::max<int64_t>(expansion, (int64_t)C.hi[c] - C.lo[c]);
         ConstructResult cr;
         TRY(construct_lattices(t, nJ, nullptr, J.p, C.kt, C.box_maxabs, expansion, C.prm.c, C.prm.gamma, C.prm.b,
-                               C.prm.seed, t, C.device, C.st, &cr));
+                               C.prm.redraw, C.prm.seed, t, C.device, C.st, &cr));
+        if (C.stats) C.stats->redraws[t - 1] = (int32_t)cr.redraws;
         const int L = (int)cr.M.size();
         int64_t sumM = 0;
         for (int64_t m : cr.M) sumM += m;
@@ -327,7 +334,8 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
             const int64_t maxM = *std::max_element(cr.M.begin(), cr.M.end());
             for (int i = 0; i < rt; ++i) {
                 sf_nodes_lattice(dM.as<int64_t>(), dOff.as<int64_t>(), dZ.as<int64_t>(), L, maxM, t, d,
-                                 dA.as<double>() + (size_t)i * d, nodes.as<double>(), C.st);
+                                 dA.as<double>() + (size_t)i * d, nodes.as<double>(),
+                                 C.dcol.p ? C.dcol.as<int>() : nullptr, C.st);
                 if (C.sampler(C.user, d, sumM, nodes.as<double>(), (char*)y.p + (size_t)i * sumM * csz, C.st) != 0) {
                     set_error("sampler callback returned an error");
                     return MR1L_ERR_CALLBACK;
@@ -386,6 +394,13 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
         sf_soa_to_rows(C.kt, prev.p, nprev, d, rows.as<int32_t>(), C.st);
         TRY(sync_check(C.st));
         MR1L_HIP_TRY(hipMemcpy(freqs_out, rows.p, (size_t)w * d * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (!C.order.empty()) {   // processing order -> the caller's components (rows keep their order)
+            std::vector<int32_t> row(d);
+            for (int64_t g = 0; g < w; ++g) {
+                for (int c = 0; c < d; ++c) row[C.order[c]] = freqs_out[g * d + c];
+                std::copy(row.begin(), row.end(), freqs_out + g * d);
+            }
+        }
         if (nfinal == nprev) MR1L_HIP_TRY(hipMemcpy(coeffs_out, final_coeffs.p, (size_t)w * 16, hipMemcpyDeviceToHost));
     }
     if (nprev > cap) {
@@ -420,6 +435,24 @@ extern "C" mr1l_status sfft_detect(int d, const int32_t* lo, const int32_t* hi, 
             box_maxabs = std::max<int64_t>(box_maxabs, std::max(std::llabs(lo[t]), std::llabs(hi[t])));
         }
         sfft_params prm = *params;
+        std::vector<int> order;
+        if (prm.order) {
+            std::vector<int> seen(d, 0);
+            bool ident = true;
+            for (int t = 0; t < d; ++t) {
+                const int o = prm.order[t];
+                if (o < 0 || o >= d || seen[o]++) {
+                    set_error("order must be a permutation of 0..d-1");
+                    return MR1L_ERR_ARG;
+                }
+                ident = ident && o == t;
+            }
+            if (!ident) order.assign(prm.order, prm.order + d);
+        }
+        if (prm.redraw < 0) {
+            set_error("redraw must be >= 0");
+            return MR1L_ERR_ARG;
+        }
         if (prm.s_local <= 0) prm.s_local = prm.s;
         if (prm.c <= 0.0) prm.c = 2.0;
         if (prm.gamma <= 0.0) prm.gamma = 0.5;
@@ -438,6 +471,18 @@ extern "C" mr1l_status sfft_detect(int d, const int32_t* lo, const int32_t* hi, 
         C.d = d;
         C.lo = lo;
         C.hi = hi;
+        if (!order.empty()) {
+            C.order = order;
+            C.plo.resize(d);
+            C.phi.resize(d);
+            for (int t = 0; t < d; ++t) {
+                C.plo[t] = lo[order[t]];
+                C.phi[t] = hi[order[t]];
+            }
+            C.lo = C.plo.data();
+            C.hi = C.phi.data();
+            if (sampler && !planted) MR1L_HIP_TRY(C.dcol.upload(order.data(), order.size() * sizeof(int)));
+        }
         C.sampler = sampler;
         C.user = user;
         C.planted = planted;
@@ -456,8 +501,9 @@ extern "C" mr1l_status sfft_detect(int d, const int32_t* lo, const int32_t* hi, 
             std::vector<int32_t> soa((size_t)std::max<int64_t>(1, s) * d);
             for (int64_t h = 0; h < s; ++h)
                 for (int c = 0; c < d; ++c) {
-                    soa[(size_t)c * s + h] = planted->freqs[h * d + c];
-                    C.pl_maxabs = std::max<int64_t>(C.pl_maxabs, std::llabs(planted->freqs[h * d + c]));
+                    const int oc = C.order.empty() ? c : C.order[c];   // processing component c
+                    soa[(size_t)c * s + h] = planted->freqs[h * d + oc];
+                    C.pl_maxabs = std::max<int64_t>(C.pl_maxabs, std::llabs(planted->freqs[h * d + oc]));
                 }
             MR1L_HIP_TRY(C.hf.upload(soa.data(), soa.size() * sizeof(int32_t)));
             MR1L_HIP_TRY(C.hc.upload(planted->coeffs, (size_t)std::max<int64_t>(1, s) * 16));

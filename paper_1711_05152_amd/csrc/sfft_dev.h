@@ -14,8 +14,8 @@ void sf_planted_wlat(int dt, const int32_t* hf, int64_t s, int d, int t, const v
                      void* w, hipStream_t st);
 void sf_add_noise(int dt, void* y, int64_t len, int nrep, const uint64_t* keys, double sigma, hipStream_t st);
 void sf_nodes_lattice(const int64_t* M, const int64_t* off, const int64_t* z, int L, int64_t maxM, int t, int d,
-                      const double* anchors, double* nodes, hipStream_t st);
-void sf_nodes_1d(int64_t K, int tc, int d, const double* anchors, double* nodes, hipStream_t st);
+                      const double* anchors, double* nodes, const int* col, hipStream_t st);
+void sf_nodes_1d(int64_t K, int tc, int d, const double* anchors, double* nodes, const int* col, hipStream_t st);
 void sf_select(int dt, const void* coeffs, int64_t n, int64_t n_rhs, double delta, int64_t s, uint8_t* flags,
                int rhs_per_group, int64_t flags_stride, hipStream_t st);
 void sf_compact(const uint8_t* flags, int64_t n, int32_t* idx, int64_t* count, hipStream_t st);

@@ -200,8 +200,9 @@ def mr1l_plan(*args, **kwargs) -> Plan:
 
 
 def mr1l_construct(freqs, c: float = 2.0, gamma: float = 0.5, b: int = 10, seed: int = 0, t: int = 0,
-                   device: int = 0):
-    """Alg. 1 with up to b calls.  Returns (M [L], z [L, d], calls, n_uncovered)."""
+                   device: int = 0, redraw: int = 0):
+    """Alg. 1 with up to b calls (redraw > 0: the variant that redraws z_L while the lattice adds
+    no reconstructible frequency).  Returns (M [L], z [L, d], calls, n_uncovered)."""
     f = np.ascontiguousarray(np.asarray(freqs, dtype=np.int32))
     n, d = f.shape
     cap = 256
@@ -210,7 +211,7 @@ def mr1l_construct(freqs, c: float = 2.0, gamma: float = 0.5, b: int = 10, seed:
     L = C.c_int(0)
     calls = C.c_int(0)
     unc = C.c_int64(0)
-    check(lib().mr1l_construct(d, n, f.ctypes.data_as(C.c_void_p), c, gamma, b, seed, t, cap, C.byref(L),
+    check(lib().mr1l_construct(d, n, f.ctypes.data_as(C.c_void_p), c, gamma, b, redraw, seed, t, cap, C.byref(L),
                                M.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p), C.byref(calls),
                                C.byref(unc), device), "mr1l_construct")
     return M[: L.value].copy(), z[: L.value].copy(), int(calls.value), int(unc.value)

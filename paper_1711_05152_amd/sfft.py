@@ -29,6 +29,7 @@ def _stats_dict(st: _lib.SfftStats) -> dict:
     return {
         "n_It": list(st.n_It[:d]), "n_J": list(st.n_J[:d]), "n_detected": list(st.n_detected[:d]),
         "L": list(st.L[:d]), "sumM": list(st.sumM[:d]), "calls": list(st.calls[:d]),
+        "redraws": list(st.redraws[:d]),
         "uncovered": list(st.uncovered[:d]), "samples": st.samples, "samples_full": st.samples_full,
         "ms_sampling": st.ms_sampling, "ms_transform": st.ms_transform, "ms_construct": st.ms_construct,
         "ms_select": st.ms_select, "ms_total": st.ms_total,
@@ -46,11 +47,13 @@ class _CudaArray:
 def sfft_detect(lo, hi, *, planted=None, sampler=None, delta: float, s: int, s_local: int = 0, r: int = 1,
                 b: int = 10, seed: int = 0, dtype: str = "c64", zero_anchors: bool = False,
                 cap: int | None = None, device: int = 0, c: float = 2.0, gamma: float = 0.5,
-                plain: bool = False) -> SfftResult:
+                plain: bool = False, redraw: int = 0, order=None) -> SfftResult:
     """Alg. 3 on the box [lo, hi].
 
     planted: (freqs int [s, d], coeffs complex [s], sigma, noise_seed) -- built-in black box;
     plain:   one transform call per repetition instead of repetitions as right-hand sides;
+    redraw:  construction variant of step 2b (> 0: redraw z_L at most this often while the lattice
+             adds no reconstructible frequency); order: component order (a permutation of 0..d-1);
     sampler: callable(nodes: torch.Tensor float64 [n, d] on the device) -> torch.Tensor complex [n]
              (used when planted is None)."""
     lo = np.ascontiguousarray(np.asarray(lo, np.int32))
@@ -60,8 +63,12 @@ def sfft_detect(lo, hi, *, planted=None, sampler=None, delta: float, s: int, s_l
     prm = _lib.SfftParams(delta=float(delta), s=int(s), s_local=int(s_local), r=int(r), b=int(b),
                           seed=int(seed) & ((1 << 64) - 1), dtype={"c64": _lib.C64, "c128": _lib.C128}[dtype],
                           c=float(c), gamma=float(gamma), zero_anchors=int(bool(zero_anchors)),
-                          plain=int(bool(plain)))
+                          plain=int(bool(plain)), redraw=int(redraw))
     keep = []
+    if order is not None:
+        ordv = np.ascontiguousarray(np.asarray(order, np.int32).reshape(d))
+        keep.append(ordv)
+        prm.order = ordv.ctypes.data
     pl_ptr = None
     if planted is not None:
         pf, pc, sigma, nseed = planted

@@ -126,3 +126,59 @@ def test_scale_d20_box32_s1000(sigma):
     print(f"sigma {sigma}: max coeff err {err.max():.3e}, samples {got.stats['samples']}, "
           f"ms {got.stats['ms_total']:.1f}", flush=True)
     assert err.max() <= (1e-4 * 10 if sigma == 0 else 1e-3)
+
+
+# ---- construction variant with redraws, component order --------------------------------------------
+
+def test_construct_redraw_matches_oracle():
+    """mr1l_construct with redraws: lattice sizes and generating vectors identical to the oracle's
+    variant (same streams, redraw a >= 1 keyed separately), and every lattice adds a frequency."""
+    require_gpu()
+    from paper_1711_05152_amd.mr1l import mr1l_construct
+    from oracle import construct as Cn
+    from oracle import mr1l as O
+    from workloads import distinct_freqs
+    hits = 0
+    for rep in range(4):
+        f = distinct_freqs(rng_for(340, rep), 900, 3, -40, 40)
+        M, z, calls, unc = mr1l_construct(f, b=10, seed=40 + rep, t=2, redraw=64)
+        stats: dict = {}
+        Mo, zo, cov, callso = Cn.construct_retry(f, b=10, seed=40 + rep, t=2, redraw=64, stats=stats)
+        assert np.array_equal(M, Mo) and np.array_equal(z, zo) and calls == callso and unc == 0
+        hits += stats.get("redraws", 0)
+    assert hits > 0   # the variant actually redrew on these sets
+
+
+def test_sfft_redraw_and_order_match_oracle():
+    """sfft_detect with the redraw variant and with a component order: detected sets, per-step
+    lattices, redraw counts and sample counts identical to the oracle's runs; a caller-supplied
+    sampler sees nodes in its own component order."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = random_planted(rng_for(341), 5, 16, 400, "box")
+    bb = PlantedBlackBox(p.freqs, p.coeffs)
+    for redraw, order in ((64, None), (0, [3, 0, 4, 2, 1]), (64, [1, 2, 0, 4, 3])):
+        got = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=1e-12, s=400, r=1, b=10, seed=77,
+                          dtype="c128", redraw=redraw, order=order, cap=400)
+        ref = oracle_sfft(p.lo, p.hi, bb, 1e-12, 400, r=1, b=10, seed=77, redraw=redraw, order=order)
+        assert np.array_equal(got.freqs, ref.freqs), (redraw, order)
+        for step in ref.steps[1:]:
+            t = step["t"]
+            assert got.stats["L"][t - 1] == step["L"] and got.stats["sumM"][t - 1] == step["sumM"]
+            assert got.stats["redraws"][t - 1] == step["redraws"], (redraw, order, t)
+        assert got.stats["samples"] == ref.samples
+        assert_close(got.coeffs, ref.coeffs, "c128", f"sfft redraw {redraw} order {order}")
+    # caller sampler, permuted order: same result as the built-in black box
+    hf = torch.from_numpy(p.freqs.astype(np.float64)).to("cuda:0")
+    hc = torch.from_numpy(p.coeffs).to("cuda:0")
+
+    def sampler(x):
+        return torch.exp(2j * np.pi * ((x @ hf.T) % 1.0)) @ hc
+
+    order = [2, 4, 0, 1, 3]
+    cb = sfft_detect(p.lo, p.hi, sampler=sampler, delta=1e-9, s=400, r=1, b=10, seed=78, dtype="c128", order=order)
+    pl = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=1e-9, s=400, r=1, b=10, seed=78,
+                     dtype="c128", order=order)
+    assert np.array_equal(cb.freqs, pl.freqs)
+    assert np.abs(cb.coeffs - pl.coeffs).max() < 1e-10
+    assert set(map(tuple, cb.freqs.tolist())) == set(map(tuple, p.freqs.tolist()))
