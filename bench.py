@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sparse-FFT, batched and gradient-descent workloads")
     ap.add_argument("--gd-steps", type=int, default=5)
+    ap.add_argument("--sweeps", type=int, default=0, metavar="REPS",
+                    help="also run the success-rate (Table 5.2 setting) and noise (Table 5.4 setting) "
+                         "sweeps with REPS seeded instances per cell")
     ap.add_argument("--emit-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="no GPU: turn the counter files of two rocprofv3 --pmc runs of this script "
                          "(FETCH_SIZE, then WRITE_SIZE, both with --copy-calibration) into the "
@@ -169,6 +172,82 @@ def extra_sfft():
                          "max_coeff_err": float(np.abs(res.coeffs - p.coeffs[order]).max()) if ok else None}
         row["batched_over_plain_time"] = row["batched"]["ms_total_median"] / row["plain"]["ms_total_median"]
         out[name] = row
+    return out
+
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+    return rows
+
+
+def _recovery(res, p):
+    """(number of planted frequencies detected, relative l2 error of the coefficient vector over
+    the union of planted and detected frequencies)."""
+    import numpy as np
+    want = {tuple(k): c for k, c in zip(p.freqs.tolist(), p.coeffs)}
+    got = {tuple(k): c for k, c in zip(res.freqs.tolist(), res.coeffs)}
+    correct = sum(1 for k in got if k in want)
+    err2 = sum(abs(got.get(k, 0.0) - c) ** 2 for k, c in want.items())
+    err2 += sum(abs(c) ** 2 for k, c in got.items() if k not in want)
+    return correct, math.sqrt(err2) / float(np.linalg.norm(p.coeffs))
+
+
+def sweep_table52(reps: int, cells=None, dtype: str = "c128"):
+    """Success rate and minimal number of correctly detected frequencies of Alg. 3 (setting of
+    Table 5.2: d = 5, N = 32, s = 1000, unit-modulus coefficients) for each (r, delta) cell, over
+    ``reps`` seeded instances, beside the paper's values from 1000 repetitions."""
+    from paper_1711_05152_amd.sfft import sfft_detect
+    from workloads import S0, sweep_t52
+    out = []
+    for r, delta, pmin, prate in _golden("table52_mlfft_success.txt"):
+        r = int(r)
+        if cells is not None and (r, delta) not in cells:
+            continue
+        ok, mins = 0, []
+        for rep in range(reps):
+            p = sweep_t52(rep)
+            res = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=delta, s=1000, r=r, b=10,
+                              seed=S0 + 52000 + rep, dtype=dtype, cap=1000)
+            correct, _ = _recovery(res, p)
+            mins.append(correct)
+            ok += correct == 1000
+        out.append({"r": r, "delta": delta, "reps": reps, "success_rate": ok / max(1, reps),
+                    "min_correct": min(mins) if mins else None, "paper_success_rate": prate,
+                    "paper_min_correct": int(pmin), "paper_reps": 1000})
+    return out
+
+
+def sweep_table54(reps: int, rows=None, dtype: str = "c128"):
+    """Alg. 3 on noisy samples (setting of Table 5.4: d = 10, N = 32, s = 1000, delta = 1e-12,
+    sigma = sqrt(s / SNR)) for each (SNR dB, r) row over ``reps`` seeded instances: maximal sample
+    count, minimal number of correctly detected frequencies, success rate, maximal relative l2
+    error, beside the paper's values from 1000 repetitions."""
+    from paper_1711_05152_amd.sfft import sfft_detect
+    from workloads import S0, sweep_t54
+    out = []
+    for snr, _sig, r, psamp, pmin, prate, perr in _golden("table54_mlfft_noise.txt"):
+        r = int(r)
+        if rows is not None and (int(snr), r) not in rows:
+            continue
+        ok, mins, errs, samples = 0, [], [], []
+        for rep in range(reps):
+            p = sweep_t54(rep, snr)
+            res = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed), delta=1e-12, s=1000,
+                              r=r, b=10, seed=S0 + 54000 + rep, dtype=dtype, cap=1000)
+            correct, err = _recovery(res, p)
+            mins.append(correct)
+            errs.append(err)
+            samples.append(res.stats["samples"])
+            ok += correct == 1000
+        out.append({"snr_db": int(snr), "sigma": math.sqrt(1000.0 / 10.0 ** (snr / 10.0)), "r": r, "reps": reps,
+                    "max_samples": max(samples) if samples else None, "min_correct": min(mins) if mins else None,
+                    "success_rate": ok / max(1, reps), "max_rel_l2_error": max(errs) if errs else None,
+                    "paper_max_samples": int(psamp), "paper_min_correct": int(pmin), "paper_success_rate": prate,
+                    "paper_max_rel_l2_error": perr, "paper_reps": 1000})
     return out
 
 
@@ -440,6 +519,10 @@ def main():
     if not args.no_extras:
         line["extra"] = {"sfft": extra_sfft(), "batched_512": extra_batched(),
                          "autograd_lsq": extra_autograd(args.gd_steps)}
+    if args.sweeps > 0:
+        t0 = time.perf_counter()
+        line["sweeps"] = {"table52_success": sweep_table52(args.sweeps), "table54_noise": sweep_table54(args.sweeps)}
+        line["sweeps"]["seconds"] = time.perf_counter() - t0
     print(json.dumps(line), flush=True)
 
 

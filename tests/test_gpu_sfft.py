@@ -5,6 +5,8 @@ oracle run with the same seed (same SplitMix64 streams on both sides); coefficie
 precision of the transforms.  The full-size d = 20 workload is checked through properties that
 hold at any size (exact support recovery, coefficient error against the planted values).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -182,3 +184,38 @@ def test_sfft_redraw_and_order_match_oracle():
     assert np.array_equal(cb.freqs, pl.freqs)
     assert np.abs(cb.coeffs - pl.coeffs).max() < 1e-10
     assert set(map(tuple, cb.freqs.tolist())) == set(map(tuple, p.freqs.tolist()))
+
+
+def _binomial_ok(k, n, p, slack=0.05):
+    """k successes of n consistent with rate p (3 standard deviations plus slack)."""
+    return abs(k / n - p) <= 3.0 * math.sqrt(max(p * (1 - p), 1e-12) / n) + slack
+
+
+def test_success_rates_match_table_5_2():
+    """Success rate of Alg. 3 on the setting of Table 5.2 (d = 5, N = 32, s = 1000, unit-modulus
+    coefficients) for cells where the paper's rate is strictly between 0 and 1 or at an end:
+    30 seeded instances per cell agree with the printed rates (1000 repetitions) within binomial
+    error.  This checks the readings of the detection steps (e.g. the 1/K factor of the 1-D
+    projections) against the paper's own runs."""
+    require_gpu()
+    import bench
+    cells = {(1, 3e-1), (1, 1e-2), (2, 3e-1), (2, 1e-1), (3, 1e-2)}
+    rows = bench.sweep_table52(30, cells)
+    assert len(rows) == len(cells)
+    for row in rows:
+        print(row, flush=True)
+        assert _binomial_ok(round(row["success_rate"] * 30), 30, row["paper_success_rate"]), row
+
+
+def test_noise_success_rates_match_table_5_4():
+    """Alg. 3 with complex Gaussian noise (setting of Table 5.4: d = 10, s = 1000, delta = 1e-12):
+    success rates over 20 instances agree with the printed ones within binomial error, and the
+    largest relative l2 error of the coefficients stays below three times the printed maximum."""
+    require_gpu()
+    import bench
+    rows = bench.sweep_table54(20, {(30, 1), (50, 1), (30, 2), (0, 5)})
+    assert len(rows) == 4
+    for row in rows:
+        print(row, flush=True)
+        assert _binomial_ok(round(row["success_rate"] * 20), 20, row["paper_success_rate"], slack=0.1), row
+        assert row["max_rel_l2_error"] <= 3 * row["paper_max_rel_l2_error"], row

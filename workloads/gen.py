@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "S0", "rng_for", "primes_between", "distinct_freqs", "cn01", "TransformProblem",
     "PlantedPoly", "transform_problem", "standalone_c2", "planted_c1", "planted_c3",
-    "batched_c4", "lsq_c5", "random_planted",
+    "batched_c4", "lsq_c5", "random_planted", "sweep_t52", "sweep_t54",
 ]
 
 S0 = 1711051520  # base seed for every synthetic workload
@@ -197,6 +197,20 @@ def batched_c4(count: int = 512, d: int = 15, box: int = 32, seed_extra: int = 0
         L = int(math.ceil(math.log2(n)))
         out.append(transform_problem(rng, n, d, box, L, n, 2 * n, with_data=with_data))
     return out
+
+
+def sweep_t52(rep: int) -> PlantedPoly:
+    """Success-rate sweep instance (setting of Table 5.2): d = 5, box [-32,32]^5, s = 1000
+    frequencies, coefficients e^{2 pi i phi}, phi uniform in [0,1); repetition ``rep``."""
+    return random_planted(rng_for(6, rep), 5, 32, 1000, "unit")
+
+
+def sweep_t54(rep: int, snr_db: float) -> PlantedPoly:
+    """Noise sweep instance (setting of Table 5.4): d = 10, box [-32,32]^10, s = 1000,
+    coefficients e^{2 pi i phi}, complex Gaussian noise with sigma = sqrt(s / SNR),
+    SNR = 10^(snr_db / 10); noise stream seeded per repetition."""
+    sigma = math.sqrt(1000.0 / 10.0 ** (snr_db / 10.0))
+    return random_planted(rng_for(7, rep), 10, 32, 1000, "unit", sigma, S0 + 7000 + rep)
 
 
 def lsq_c5(n: int = 1 << 20, d: int = 30, box: int = 16, L: int = 20, n_rhs: int = 64):
