@@ -218,6 +218,7 @@ def sweep_table52(reps: int, cells=None, dtype: str = "c128"):
         out.append({"r": r, "delta": delta, "reps": reps, "success_rate": ok / max(1, reps),
                     "min_correct": min(mins) if mins else None, "paper_success_rate": prate,
                     "paper_min_correct": int(pmin), "paper_reps": 1000})
+        print("sweep table 5.2 cell", json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
 
 
@@ -248,6 +249,7 @@ def sweep_table54(reps: int, rows=None, dtype: str = "c128"):
                     "success_rate": ok / max(1, reps), "max_rel_l2_error": max(errs) if errs else None,
                     "paper_max_samples": int(psamp), "paper_min_correct": int(pmin), "paper_success_rate": prate,
                     "paper_max_rel_l2_error": perr, "paper_reps": 1000})
+        print("sweep table 5.4 row", json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
 
 
