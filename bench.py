@@ -349,6 +349,10 @@ def extra_autograd(steps: int):
             "loss_monotone": all(b <= a for a, b in zip(losses, losses[1:]))}
 
 
+def _progress(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def fft_flops(N: int) -> float:
     """Nominal cost of a complex FFT of length N (5 N log2 N)."""
     return 5.0 * N * math.log2(N) if N > 1 else 0.0
@@ -414,6 +418,7 @@ def main():
     torch.cuda.synchronize()
     ms_cached = ev4.elapsed_time(ev5) / args.steps
     plan.cache_alias(False)
+    _progress(f"headline timed: {ms_event:.4f} ms/step, plan-cached {ms_cached:.4f} ms/step")
 
     # per-stage device time: HIP events recorded by the library on the stream of each launch, over
     # a second timed loop of the same steps (its own step time is reported beside the plain one)
@@ -487,6 +492,7 @@ def main():
             if time.perf_counter() - tc0 > args.cpu_seconds:
                 break
         tcpu = (time.perf_counter() - tc0) / iters
+        _progress(f"cpu oracle baseline: {iters} pairs, {tcpu:.3f} s each")
         cpu = {"value": n / tcpu, "unit": "freqs/s", "cores": threads, "kind": "oracle",
                "sample": f"{iters} forward+adjoint pairs of the same |I|=2^16 workload (numpy FFT tier, "
                          f"FP64), {tcpu:.3f} s each"}
@@ -519,8 +525,13 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_extras:
-        line["extra"] = {"sfft": extra_sfft(), "batched_512": extra_batched(),
-                         "autograd_lsq": extra_autograd(args.gd_steps)}
+        extra = {"sfft": extra_sfft()}
+        _progress("sparse FFT solve timed")
+        extra["batched_512"] = extra_batched()
+        _progress("batched transforms timed")
+        extra["autograd_lsq"] = extra_autograd(args.gd_steps)
+        _progress("gradient-descent steps timed")
+        line["extra"] = extra
     if args.sweeps > 0:
         t0 = time.perf_counter()
         line["sweeps"] = {"table52_success": sweep_table52(args.sweeps), "table54_noise": sweep_table54(args.sweeps)}
