@@ -19,4 +19,7 @@ multiple rank-1 lattices" (arXiv 1711.05152) that it follows:
                 distinct prime sizes (Alg. 1) and the parameter rules around it.
 * ``sfft``      the dimension-incremental sparse FFT (Alg. 3 "MLFFT") with the planted
                 polynomial black box, 1-D projections, thresholding and top-s selection.
+* ``bspline``   the periodic B-splines N_m and the tensor-product test function of Sec. 5.3
+                (point values, Fourier coefficients, norm, relative L2 approximation error),
+                usable as a black box of ``sfft``.
 """

@@ -46,7 +46,7 @@ from . import rng as R
 from .construct import construct_retry
 from .mr1l import forward, forward_direct, residues, sample_offsets, lattice_nodes
 
-__all__ = ["PlantedBlackBox", "select_top", "projection_1d", "sfft", "SfftResult"]
+__all__ = ["PlantedBlackBox", "select_top", "decision_margin", "projection_1d", "sfft", "SfftResult"]
 
 
 def _sqabs(v: np.ndarray) -> np.ndarray:
@@ -54,6 +54,20 @@ def _sqabs(v: np.ndarray) -> np.ndarray:
     re = v.real.copy()
     im = v.imag.copy()
     return re * re + im * im
+
+
+def decision_margin(vals: np.ndarray, delta: float, s: int) -> float:
+    """Smallest relative distance of a selection decision of ``select_top`` from a flip: of each
+    |v|^2 from delta^2, and, when more than s pass the threshold, of the s-th largest from the
+    (s+1)-th.  inf when nothing is decided by a comparison of values."""
+    key = _sqabs(vals)
+    m = np.inf
+    if delta > 0.0 and len(key):
+        m = float(np.min(np.abs(key - delta * delta)) / (delta * delta))
+    above = np.sort(key[key >= delta * delta])[::-1]
+    if len(above) > s >= 1:
+        m = min(m, float((above[s - 1] - above[s]) / max(above[s - 1], np.finfo(float).tiny)))
+    return m
 
 
 def select_top(vals: np.ndarray, delta: float, s: int) -> np.ndarray:
@@ -144,20 +158,23 @@ class SfftResult:
     steps: list = field(default_factory=list)
     samples: int = 0            # distinct nodes: sum over steps of r K_t and r~ (1 - L + sum M)
     samples_full: int = 0       # values drawn when every lattice is sampled in full
+    margin: float = np.inf      # smallest decision_margin over every selection of the run
 
 
 def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = None,
          r: int = 1, b: int = 10, seed: int = 0, tier: int = 1, zero_anchors: bool = False,
-         redraw: int = 0, order=None) -> SfftResult:
+         redraw: int = 0, order=None, delta_1d: float | None = None) -> SfftResult:
     """Alg. 3 on the box search space [box_lo, box_hi] (inclusive, per component).
     ``zero_anchors``: anchor components fixed to 0 instead of drawn (the r = 1 setting of the
     remark on coefficients with a common sign of real or imaginary part, Sec. 3.1).
-    ``redraw``: construction variant (see ``oracle.construct``); ``order``: component order."""
+    ``redraw``: construction variant (see ``oracle.construct``); ``order``: component order.
+    ``delta_1d``: threshold of the 1-D detections (steps 1 and 2a) when it differs from
+    ``delta`` (the threshold-based truncation of Sec. 5.3 uses delta / 10 there)."""
     if order is not None and list(order) != list(range(len(box_lo))):
         order = np.asarray(order, np.int64)
         assert sorted(order.tolist()) == list(range(len(box_lo))), "order must be a permutation"
         res = sfft(np.asarray(box_lo)[order], np.asarray(box_hi)[order], black_box.permuted(order), delta, s,
-                   s_local, r, b, seed, tier, zero_anchors, redraw, None)
+                   s_local, r, b, seed, tier, zero_anchors, redraw, None, delta_1d)
         orig = np.empty_like(res.freqs)
         orig[:, order] = res.freqs
         res.freqs = orig
@@ -166,6 +183,7 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
     hi = np.asarray(box_hi, np.int64)
     d = len(lo)
     s_local = s if s_local is None else s_local
+    delta_1d = delta if delta_1d is None else delta_1d
     res = SfftResult(np.zeros((0, d), np.int32), np.zeros(0, np.complex128))
 
     def detect_1d(t):
@@ -177,7 +195,8 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
             anchors = np.zeros(d) if zero_anchors else np.array([R.uniform01(k1, c) for c in range(d)])
             y = black_box.sample_1d(t, i, anchors, K)
             pt = projection_1d(y, int(lo[t - 1]), int(hi[t - 1]))
-            flags[select_top(pt, delta, s_local)] = True
+            flags[select_top(pt, delta_1d, s_local)] = True
+            res.margin = min(res.margin, decision_margin(pt, delta_1d, s_local))
             last = pt
         res.samples += r * K
         res.samples_full += r * K
@@ -211,6 +230,7 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
             y = black_box.sample_lattice(t, i, M, z, tail, tier=tier)
             pt = forward(J, M, z, y) if tier == 1 else forward_direct(J, M, z, y)
             flags[select_top(pt, delta, s_t)] = True
+            res.margin = min(res.margin, decision_margin(pt, delta, s_t))
             last_coeffs = pt
             res.samples += 1 - len(M) + int(np.sum(M))
             res.samples_full += int(np.sum(M))
