@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=0, metavar="REPS",
                     help="also run the success-rate (Table 5.2 setting) and noise (Table 5.4 setting) "
                          "sweeps with REPS seeded instances per cell")
+    ap.add_argument("--bspline-sweeps", type=int, default=0, metavar="REPS",
+                    help="also run the B-spline test function sweeps (settings of Tables 5.7 and 5.8) with REPS "
+                         "seeds per row")
+    ap.add_argument("--bspline-max-N", type=int, default=64,
+                    help="largest expansion N of the threshold-truncation rows")
     ap.add_argument("--emit-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="no GPU: turn the counter files of two rocprofv3 --pmc runs of this script "
                          "(FETCH_SIZE, then WRITE_SIZE, both with --copy-calibration) into the "
@@ -250,6 +255,68 @@ def sweep_table54(reps: int, rows=None, dtype: str = "c128"):
                     "paper_max_samples": int(psamp), "paper_min_correct": int(pmin), "paper_success_rate": prate,
                     "paper_max_rel_l2_error": perr, "paper_reps": 1000})
         print("sweep table 5.4 row", json.dumps(out[-1]), file=sys.stderr, flush=True)
+    return out
+
+
+def sweep_table57(reps: int, rows=None, dtype: str = "c128"):
+    """Alg. 3 on the 10-variate B-spline test function of Sec. 5.3 with s-sparse truncation (setting
+    of Table 5.7: search space [-N,N]^10, r = 5, delta = 1e-12, s_local = 2s) for each (N, s) row
+    over ``reps`` seeds: maximal sample count and maximal relative L2 error (the library's Parseval
+    formula), median solve time, beside the paper's Alg. 3 values from 10 runs."""
+    import numpy as np
+    from paper_1711_05152_amd.sfft import paper_f10, sfft_detect
+    from workloads import S0
+    f = paper_f10(dtype)
+    out = []
+    for N, s, a5s, a5e, a3s, a3e, a4s, a4e in _golden("table57_bspline_ssparse.txt"):
+        N, s = int(N), int(s)
+        if rows is not None and (N, s) not in rows:
+            continue
+        errs, samples, ms, sizes = [], [], [], []
+        for rep in range(reps):
+            res = sfft_detect([-N] * 10, [N] * 10, bspline=f, delta=1e-12, s=s, s_local=2 * s, r=5, b=10,
+                              seed=S0 + 57000 + rep, dtype=dtype, cap=s)
+            errs.append(f.rel_l2_error(res.freqs, res.coeffs)[0])
+            samples.append(res.stats["samples"])
+            ms.append(res.stats["ms_total"])
+            sizes.append(len(res.freqs))
+        out.append({"N": N, "s": s, "reps": reps, "max_samples": max(samples), "max_rel_l2_error": max(errs),
+                    "max_I": max(sizes), "ms_total_median": float(np.median(ms)),
+                    "paper_alg3_max_samples": int(a3s), "paper_alg3_max_rel_l2_error": a3e,
+                    "paper_alg5_max_samples": int(a5s), "paper_alg4_max_samples": int(a4s), "paper_reps": 10})
+        print("sweep table 5.7 row", json.dumps(out[-1]), file=sys.stderr, flush=True)
+    return out
+
+
+def sweep_table58(reps: int, rows=None, dtype: str = "c128", max_N: int = 1 << 30):
+    """Alg. 3 on the B-spline test function with threshold truncation (setting of Table 5.8: search
+    space [-N,N]^10, r = 10, s = |Gamma| (no sparsity cut), delta = threshold / 10 in the 1-D
+    detections and delta = threshold elsewhere) over ``reps`` seeds: maximal |I|, maximal sample
+    count, maximal relative L2 error and median solve time.  The paper prints Alg. 5 and Alg. 4
+    columns for this table (no Alg. 3 column); both are carried along for context."""
+    import numpy as np
+    from paper_1711_05152_amd.sfft import paper_f10, sfft_detect
+    from workloads import S0
+    f = paper_f10(dtype)
+    out = []
+    for N, thr, a5i, a5s, a5e, a4i, a4s, a4e in _golden("table58_bspline_threshold.txt"):
+        N = int(N)
+        if N > max_N or (rows is not None and (N, thr) not in rows):
+            continue
+        errs, samples, ms, sizes = [], [], [], []
+        for rep in range(reps):
+            res = sfft_detect([-N] * 10, [N] * 10, bspline=f, delta=thr, delta_1d=thr / 10, s=1 << 62, r=10, b=10,
+                              seed=S0 + 58000 + rep, dtype=dtype, cap=1 << 19)
+            errs.append(f.rel_l2_error(res.freqs, res.coeffs)[0])
+            samples.append(res.stats["samples"])
+            ms.append(res.stats["ms_total"])
+            sizes.append(len(res.freqs))
+        out.append({"N": N, "threshold": thr, "reps": reps, "max_I": max(sizes), "max_samples": max(samples),
+                    "max_rel_l2_error": max(errs), "ms_total_median": float(np.median(ms)),
+                    "paper_alg5": {"max_I": int(a5i), "max_samples": int(a5s), "max_rel_l2_error": a5e},
+                    "paper_alg4": {"max_I": int(a4i), "max_samples": int(a4s), "max_rel_l2_error": a4e},
+                    "paper_reps": 10})
+        print("sweep table 5.8 row", json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
 
 
@@ -536,6 +603,11 @@ def main():
         t0 = time.perf_counter()
         line["sweeps"] = {"table52_success": sweep_table52(args.sweeps), "table54_noise": sweep_table54(args.sweeps)}
         line["sweeps"]["seconds"] = time.perf_counter() - t0
+    if args.bspline_sweeps > 0:
+        t0 = time.perf_counter()
+        line["bspline_sweeps"] = {"table57_ssparse": sweep_table57(args.bspline_sweeps),
+                                  "table58_threshold": sweep_table58(args.bspline_sweeps, max_N=args.bspline_max_N)}
+        line["bspline_sweeps"]["seconds"] = time.perf_counter() - t0
     print(json.dumps(line), flush=True)
 
 

@@ -180,6 +180,43 @@ typedef struct sfft_planted {
     uint64_t noise_seed;
 } sfft_planted;
 
+/* Built-in test function of Sec. 5.3: f(x) = sum_tau w_tau prod_c N_{m(tau,c)}(x_c), a weighted sum
+ * of tensor products of the periodic B-splines
+ *     N_m(x) = C_m sum_{k in Z} sinc(pi k/m)^m (-1)^k e^{2 pi i k x},  ||N_m||_{L2(T)} = 1,
+ * (factor 1 where the order is 0).  The test function on T^10 of Sec. 5.3 has three terms: order 2 on
+ * components 1, 3, 8, order 4 on 2, 5, 6, 10 and order 6 on 4, 7, 9 (1-based), all weights 1. */
+#define SFFT_BSPLINE_MAX_TERMS 8
+#define SFFT_BSPLINE_MAX_ORDER 12
+typedef struct sfft_bspline {
+    int terms;               /* number of products, 1..SFFT_BSPLINE_MAX_TERMS    */
+    int d;                   /* dimension, 1..SFFT_MAX_D                         */
+    const int32_t* orders;   /* host int32 [terms][d]: order m (0..12) of the
+                                factor of component c in product tau, 0 = none    */
+    const double* weights;   /* host double [terms], or NULL for all ones        */
+    mr1l_dtype dtype;        /* complex type of the values the sampler writes    */
+} sfft_bspline;
+
+/* Sampler of the built-in test function (signature of sfft_sampler_fn; pass it to sfft_detect with
+ * user = a const sfft_bspline*).  Writes values_dev[j] = (f(nodes_dev[j]), 0) for j < n_nodes with
+ * one kernel enqueued on ``stream`` (a hipStream_t, NULL for the default stream); nodes may lie
+ * anywhere on R^d (taken mod 1).  Allocates nothing.  Returns 0, or 1 for an invalid description
+ * (orders outside 0..12, d not matching) or a failed launch (mr1l_last_error() tells which). */
+int sfft_sample_bspline(void* user, int d, int64_t n_nodes, const double* nodes_dev, void* values_dev,
+                        void* stream);
+
+/* Fourier coefficients f^_k = sum_tau w_tau prod_c g^_{tau,c}(k_c) of the test function (Sec. 5.3),
+ * g^ = N^_m for a factor N_m, the indicator of k_c = 0 for a factor 1.
+ *   freqs   host int32 [n][d];   coeffs  host double [n][2] (re, im; im is 0).  Host only. */
+mr1l_status sfft_bspline_coeffs(const sfft_bspline* f, int64_t n, const int32_t* freqs, double* coeffs);
+
+/* Relative L2(T^d) approximation error of p = sum_{k in I} p~_k e^{2 pi i k.x}, I = rows of freqs
+ * (Sec. 5.3, by Parseval):
+ *   ||f - p|| / ||f|| = sqrt(||f||^2 - sum_I |f^_k|^2 + sum_I |p~_k - f^_k|^2) / ||f||.
+ *   freqs   host int32 [n][d] (distinct);  coeffs  host double [n][2];  rel_err  out;
+ *   norm2   optional out, ||f||^2.  Host only. */
+mr1l_status sfft_bspline_l2_error(const sfft_bspline* f, int64_t n, const int32_t* freqs, const double* coeffs,
+                                  double* rel_err, double* norm2);
+
 typedef struct sfft_params {
     double delta;            /* absolute threshold                               */
     int64_t s;               /* sparsity of the output                           */
@@ -199,6 +236,9 @@ typedef struct sfft_params {
                                 order may be used).  Stream keys follow the step;
                                 output rows hold the original components, listed
                                 lexicographically in the processing order        */
+    double delta_1d;         /* threshold of the 1-D detections (steps 1 and 2a);
+                                0: delta.  The threshold-based truncation of
+                                Sec. 5.3 uses delta / 10 there                   */
 } sfft_params;
 
 #define SFFT_MAX_D 64

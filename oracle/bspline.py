@@ -6,7 +6,7 @@ The univariate factor (Sec. 5.3) is the periodic B-spline of order m,
 
     N_m(x) = C_m sum_{k in Z} sinc(pi k / m)^m (-1)^k e^{2 pi i k x},   sinc(u) = sin(u) / u,
 
-with C_m > 0 chosen so that the L2(T) norm of N_m is one.  The test function of eq. (5.1) is
+with C_m > 0 chosen so that the L2(T) norm of N_m is one.  The test function of the section is
 
     f(x) = prod_{t in {1,3,8}} N_2(x_t) + prod_{t in {2,5,6,10}} N_4(x_t) + prod_{t in {4,7,9}} N_6(x_t)
 
@@ -109,7 +109,7 @@ def _inner(m1: int, m2: int) -> float:
 
 
 def paper_f10_orders() -> np.ndarray:
-    """orders matrix of the test function of eq. (5.1) on T^10 (components 1-based in the paper)."""
+    """orders matrix of the test function of Sec. 5.3 on T^10 (components 1-based in the paper)."""
     o = np.zeros((3, 10), np.int32)
     for t in (1, 3, 8):
         o[0, t - 1] = 2

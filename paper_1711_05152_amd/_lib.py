@@ -17,7 +17,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OVERFLOW", 3: "ERR_NOMEM", 4: "ERR_HIP"
 
 EXPORTED = ["mr1l_plan", "mr1l_plan_batched", "mr1l_forward", "mr1l_adjoint", "mr1l_alias", "mr1l_info", "mr1l_destroy",
             "mr1l_timing_enable", "mr1l_timing_read", "mr1l_cache_alias", "mr1l_construct", "sfft_detect",
-            "mr1l_last_error", "mr1l_version"]
+            "sfft_sample_bspline", "sfft_bspline_coeffs", "sfft_bspline_l2_error", "mr1l_last_error", "mr1l_version"]
 
 
 class Mr1lError(RuntimeError):
@@ -38,7 +38,16 @@ class SfftParams(C.Structure):
     _fields_ = [("delta", C.c_double), ("s", C.c_int64), ("s_local", C.c_int64), ("r", C.c_int),
                 ("b", C.c_int), ("seed", C.c_uint64), ("dtype", C.c_int), ("c", C.c_double),
                 ("gamma", C.c_double), ("zero_anchors", C.c_int), ("plain", C.c_int), ("redraw", C.c_int),
-                ("order", C.c_void_p)]
+                ("order", C.c_void_p), ("delta_1d", C.c_double)]
+
+
+SFFT_BSPLINE_MAX_TERMS = 8
+SFFT_BSPLINE_MAX_ORDER = 12
+
+
+class SfftBspline(C.Structure):
+    _fields_ = [("terms", C.c_int), ("d", C.c_int), ("orders", C.c_void_p), ("weights", C.c_void_p),
+                ("dtype", C.c_int)]
 
 
 SFFT_MAX_D = 64
@@ -81,6 +90,9 @@ def lib() -> C.CDLL:
                            C.POINTER(i32), C.POINTER(i64), i32],
         "sfft_detect": [i32, vp, vp, SAMPLER_FN, vp, C.POINTER(SfftPlanted), C.POINTER(SfftParams), i64,
                         C.POINTER(i64), vp, vp, C.POINTER(SfftStats), i32],
+        "sfft_sample_bspline": [vp, i32, i64, vp, vp, vp],
+        "sfft_bspline_coeffs": [C.POINTER(SfftBspline), i64, vp, vp],
+        "sfft_bspline_l2_error": [C.POINTER(SfftBspline), i64, vp, vp, C.POINTER(dbl), C.POINTER(dbl)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -166,7 +166,7 @@ mr1l_status detect_1d(Ctx& C, std::vector<DevMem>& It, std::vector<int64_t>& nIt
         t0 = clk::now();
         MR1L_HIP_TRY(flags.alloc((size_t)ts.size() * K));
         MR1L_HIP_TRY(hipMemsetAsync(flags.p, 0, (size_t)ts.size() * K, C.st));
-        sf_select(C.prm.dtype, coeffs.p, K, njobs, C.prm.delta, C.prm.s_local, flags.as<uint8_t>(), r, K, C.st);
+        sf_select(C.prm.dtype, coeffs.p, K, njobs, C.prm.delta_1d, C.prm.s_local, flags.as<uint8_t>(), r, K, C.st);
         MR1L_HIP_TRY(idx.alloc((size_t)K * sizeof(int32_t)));
         MR1L_HIP_TRY(cnt.alloc(sizeof(int64_t)));
         for (size_t a = 0; a < ts.size(); ++a) {
@@ -454,9 +454,10 @@ extern "C" mr1l_status sfft_detect(int d, const int32_t* lo, const int32_t* hi, 
             return MR1L_ERR_ARG;
         }
         if (prm.s_local <= 0) prm.s_local = prm.s;
+        if (prm.delta_1d == 0.0) prm.delta_1d = prm.delta;
         if (prm.c <= 0.0) prm.c = 2.0;
         if (prm.gamma <= 0.0) prm.gamma = 0.5;
-        if (!(prm.delta >= 0.0) || prm.s < 1 || prm.r < 1 || prm.b < 1 || !(prm.c > 1.0) || !(prm.gamma < 1.0) ||
+        if (!(prm.delta >= 0.0) || !(prm.delta_1d >= 0.0) || prm.s < 1 || prm.r < 1 || prm.b < 1 || !(prm.c > 1.0) || !(prm.gamma < 1.0) ||
             (prm.dtype != MR1L_C64 && prm.dtype != MR1L_C128)) {
             set_error("invalid sfft_params");
             return MR1L_ERR_ARG;

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "mr1l.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^(?:mr1l_status|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^(?:mr1l_status|const char\*|int)\s+(\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
@@ -62,7 +62,8 @@ def test_struct_layouts_match_the_binding(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
-    structs = {"sfft_params": _lib.SfftParams, "sfft_stats": _lib.SfftStats, "sfft_planted": _lib.SfftPlanted}
+    structs = {"sfft_params": _lib.SfftParams, "sfft_stats": _lib.SfftStats, "sfft_planted": _lib.SfftPlanted,
+               "sfft_bspline": _lib.SfftBspline}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mr1l.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
