@@ -129,6 +129,19 @@ mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_unco
  * Errors: MR1L_ERR_ARG for a NULL plan. */
 mr1l_status mr1l_cache_alias(mr1l_plan_t plan, int enable);
 
+/* Device-memory cache.  Every device buffer of the library (plan work areas, sparse-FFT steps)
+ * comes from a per-device cache of size-classed blocks: a released block stays mapped and serves
+ * later requests of its class, because allocating and freeing multi-GB regions through the driver
+ * costs up to seconds per call once device memory has been churned.  Idle bytes per device are
+ * capped (default: a quarter of the device's memory); a request that finds the device full
+ * empties the cache and retries.
+ *   device          device whose cache is addressed
+ *   max_idle_bytes  new cap (0 disables caching); < 0 keeps the current cap
+ *   released        optional out: bytes returned to the driver by this call
+ * Returns every idle block of the device to the driver (after a device-wide synchronisation) and
+ * then applies the cap.  Errors: MR1L_ERR_ARG for an invalid device. */
+mr1l_status mr1l_memory_cache(int device, int64_t max_idle_bytes, int64_t* released);
+
 /* Release a plan and its device memory (NULL is accepted). */
 mr1l_status mr1l_destroy(mr1l_plan_t plan);
 

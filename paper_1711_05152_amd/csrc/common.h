@@ -214,7 +214,7 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
 // (wrapped), stored in the layout stage 2 reads (natural order on the one-block path,
 // [k1][k2] = B[k1 + N1 k2] on the four-step path).
 template <typename T>
-void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std::vector<FftGroup>& groups,
-                   cx<T>* filt, int device, hipStream_t s);
+hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std::vector<FftGroup>& groups,
+                         cx<T>* filt, int device, hipStream_t s);
 
 }  // namespace mr1l

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.h"
+#include "runtime.h"
 
 namespace mr1l {
 
@@ -845,17 +846,19 @@ MR1L_INST_FFT(double)
 // b_l reuses the stage-1/stage-2 kernels (or the one-block DFT) on a temporary buffer laid out
 // like the work area; the four-step split is the one the plan's own stage 2 reads.
 template <typename T>
-void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std::vector<FftGroup>& groups,
-                   cx<T>* filt, int device, hipStream_t s) {
-    if (L == 0) return;
+hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std::vector<FftGroup>& groups,
+                         cx<T>* filt, int device, hipStream_t s) {
+    if (L == 0) return hipSuccess;
     int64_t tot = 0;
     int maxlg = 0;
     for (int l = 0; l < L; ++l) {
         tot = std::max<int64_t>(tot, hdesc[l].work_off + ((int64_t)1 << hdesc[l].lgN));
         maxlg = std::max(maxlg, hdesc[l].lgN);
     }
-    cx<double>* tmp = nullptr;
-    (void)hipMalloc(&tmp, tot * sizeof(cx<double>));
+    DevMem tmpm;
+    hipError_t e = tmpm.alloc((size_t)tot * sizeof(cx<double>));
+    if (e != hipSuccess) return e;
+    cx<double>* tmp = tmpm.as<cx<double>>();
     TxArgs a{};
     a.desc = ddesc;
     a.L = L;
@@ -882,12 +885,11 @@ void build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, const std:
         }
     }
     hipLaunchKernelGGL((k_filter_store<T>), dim3(blocks, L), dim3(256), 0, s, ddesc, (const cx<double>*)tmp, filt);
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(tmp);
+    return hipStreamSynchronize(s);
 }
-template void build_filters<float>(const LatDesc*, int, const LatDesc*, const std::vector<FftGroup>&, cx<float>*, int,
+template hipError_t build_filters<float>(const LatDesc*, int, const LatDesc*, const std::vector<FftGroup>&, cx<float>*, int,
                                    hipStream_t);
-template void build_filters<double>(const LatDesc*, int, const LatDesc*, const std::vector<FftGroup>&, cx<double>*,
+template hipError_t build_filters<double>(const LatDesc*, int, const LatDesc*, const std::vector<FftGroup>&, cx<double>*,
                                     int, hipStream_t);
 
 }  // namespace mr1l

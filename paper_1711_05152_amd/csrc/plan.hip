@@ -336,7 +336,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         set_error("could not allocate twiddle tables");
         return MR1L_ERR_NOMEM;
     }
-    if (!sh) build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, (cx<T>*)P->filt_ptr, sp.device, nullptr);
+    if (!sh) MR1L_HIP_TRY(build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, (cx<T>*)P->filt_ptr, sp.device, nullptr));
     MR1L_HIP_TRY(hipGetLastError());
     MR1L_HIP_TRY(hipDeviceSynchronize());
     *out = guard.release();

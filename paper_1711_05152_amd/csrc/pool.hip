@@ -1,0 +1,162 @@
+// Caching device allocator behind every DevMem of the library.
+//
+// Plans and the steps of the sparse FFT allocate and free work areas of up to tens of GB.  Once
+// device memory has been through a few such cycles, the driver's hipMalloc / hipFree of those sizes
+// take 50 ms to seconds per call (measured: single hipMalloc calls of 2.4 s, hipFree calls of
+// 50-110 ms, against a few ms of kernels per step).  Freed blocks are therefore kept mapped, per
+// device, in size classes and handed out again:
+//   * classes: powers of two up to 2 MiB; above, eight classes per octave rounded to 2 MiB (at most
+//     12.5 % slack);
+//   * a freed block may still be read or written by work queued before the free (hipFree waited
+//     for the device, the cache does not), so it is "pending" until the next device-wide
+//     synchronisation; the cache synchronises only when a request finds no ready block of its
+//     class but a pending one;
+//   * idle bytes per device are capped (default a quarter of the device's memory, see
+//     mr1l_memory_cache); a free beyond the cap goes back to the driver;
+//   * a hipMalloc that fails for lack of memory empties the device's cache and is retried once.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "runtime.h"
+
+namespace mr1l {
+namespace {
+
+struct DevCache {
+    std::multimap<size_t, void*> ready, pending;
+    size_t idle = 0;       // bytes held in ready + pending
+    int64_t limit = -1;    // cap on idle bytes; -1 until first use
+};
+
+std::mutex g_mu;
+std::vector<DevCache> g_cache;
+
+size_t size_class(size_t b) {
+    constexpr size_t kMiB2 = (size_t)2 << 20;
+    if (b <= kMiB2) {
+        size_t c = 256;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    const int k = 63 - __builtin_clzll((unsigned long long)b);     // 2^k <= b < 2^(k+1)
+    const size_t step = ((size_t)1 << k) / 8;
+    size_t c = (b + step - 1) / step * step;
+    return (c + kMiB2 - 1) / kMiB2 * kMiB2;
+}
+
+// caller holds g_mu
+DevCache& cache_of(int dev) {
+    if ((int)g_cache.size() <= dev) g_cache.resize(dev + 1);
+    DevCache& C = g_cache[dev];
+    if (C.limit < 0) {
+        size_t fr = 0, tot = 0;
+        C.limit = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(tot / 4) : 0;
+    }
+    return C;
+}
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// caller holds g_mu; returns the bytes given back to the driver
+size_t trim_locked(int dev) {
+    DevCache& C = cache_of(dev);
+    if (C.ready.empty() && C.pending.empty()) return 0;
+    DeviceScope ds(dev);
+    (void)hipDeviceSynchronize();
+    size_t freed = 0;
+    for (auto* m : {&C.ready, &C.pending}) {
+        for (auto& kv : *m) {
+            (void)hipFree(kv.second);
+            freed += kv.first;
+        }
+        m->clear();
+    }
+    C.idle = 0;
+    return freed;
+}
+
+}  // namespace
+
+hipError_t pool_alloc(void** p, size_t bytes, int* dev_out) {
+    *p = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    *dev_out = dev;
+    const size_t c = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DevCache& C = cache_of(dev);
+        auto it = C.ready.find(c);
+        if (it == C.ready.end() && C.pending.count(c)) {
+            // every pending block becomes reusable once the device has drained
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) return e;
+            C.ready.insert(C.pending.begin(), C.pending.end());
+            C.pending.clear();
+            it = C.ready.find(c);
+        }
+        if (it != C.ready.end()) {
+            *p = it->second;
+            C.ready.erase(it);
+            C.idle -= c;
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, c);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            trim_locked(dev);
+        }
+        e = hipMalloc(p, c);
+    }
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
+void pool_free(void* p, size_t bytes, int dev) {
+    if (!p) return;
+    const size_t c = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DevCache& C = cache_of(dev);
+        if ((int64_t)(C.idle + c) <= C.limit) {
+            C.pending.insert({c, p});
+            C.idle += c;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
+}  // namespace mr1l
+
+using namespace mr1l;
+
+extern "C" mr1l_status mr1l_memory_cache(int device, int64_t max_idle_bytes, int64_t* released) {
+    clear_error();
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        set_error("invalid device for mr1l_memory_cache");
+        return MR1L_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    const size_t freed = trim_locked(device);
+    if (max_idle_bytes >= 0) cache_of(device).limit = max_idle_bytes;
+    if (released) *released = (int64_t)freed;
+    return MR1L_OK;
+}

@@ -24,38 +24,48 @@ void clear_error();
         }                                                                                            \
     } while (0)
 
-// Owning device allocation.
+// Caching device allocator (pool.hip): every DevMem goes through it.
+hipError_t pool_alloc(void** p, size_t bytes, int* dev);
+void pool_free(void* p, size_t bytes, int dev);
+
+// Owning device allocation (size-classed, cached per device; see pool.hip).
 struct DevMem {
     void* p = nullptr;
     size_t bytes = 0;
+    int dev = -1;
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
-    DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) {
+    DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) {
         o.p = nullptr;
         o.bytes = 0;
+        o.dev = -1;
     }
     DevMem& operator=(DevMem&& o) noexcept {
         if (this != &o) {
             release();
             p = o.p;
             bytes = o.bytes;
+            dev = o.dev;
             o.p = nullptr;
             o.bytes = 0;
+            o.dev = -1;
         }
         return *this;
     }
     ~DevMem() { release(); }
     void release() {
-        if (p) hipFree(p);
+        if (p) pool_free(p, bytes, dev);
         p = nullptr;
         bytes = 0;
+        dev = -1;
     }
     hipError_t alloc(size_t b) {
         release();
-        bytes = b;
         if (b == 0) return hipSuccess;
-        return hipMalloc(&p, b);
+        hipError_t e = pool_alloc(&p, b, &dev);
+        if (e == hipSuccess) bytes = b;
+        return e;
     }
     hipError_t upload(const void* h, size_t b) {
         hipError_t e = alloc(b);

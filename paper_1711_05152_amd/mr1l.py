@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "version"]
+__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "memory_cache", "version"]
 
 _DT = {"c64": (_lib.C64, torch.complex64), "c128": (_lib.C128, torch.complex128)}
 _W = {"paper": _lib.W_PAPER, "eval": _lib.W_EVAL}
@@ -29,6 +29,14 @@ def _ptr(t: torch.Tensor | None) -> C.c_void_p:
 
 def version() -> str:
     return lib().mr1l_version().decode()
+
+
+def memory_cache(device: int = 0, max_idle_bytes: int = -1) -> int:
+    """Return the idle blocks of the library's device-memory cache on ``device`` to the driver and
+    set the cap on idle bytes (< 0 keeps it, 0 disables caching); returns the bytes released."""
+    out = C.c_int64(0)
+    check(lib().mr1l_memory_cache(int(device), int(max_idle_bytes), C.byref(out)), "mr1l_memory_cache")
+    return int(out.value)
 
 
 class Plan:

@@ -236,3 +236,34 @@ def test_eval_adjoint_crowded_bins():
     plan = _plan(p, "c128", "eval")
     y = plan.adjoint(_to(torch, p.coeffs, "c128"))
     assert_close(y.cpu().numpy(), O.adjoint(p.freqs, p.M, p.z, p.coeffs, "eval"), "c128", "crowded eval adjoint")
+
+
+def test_memory_cache_reuse_and_release():
+    """Plans created one after another reuse the library's cached device blocks (stale contents
+    included) and give the same results; the cache gives its idle blocks back on request and can be
+    switched off."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import memory_cache
+    name, n, d, box, L, mlo, mhi, n_rhs = CASES[3]
+    p = transform_problem(rng_for(302, 7), n, d, box, L, mlo, mhi, n_rhs=n_rhs)
+    y = _to(torch, p.samples, "c128")
+    c_ref = O.forward(p.freqs, p.M, p.z, p.samples, "paper")
+    memory_cache(0)
+    outs = []
+    for _ in range(3):
+        plan = _plan(p, "c128")
+        outs.append(plan.forward(y).cpu().numpy())
+        del plan
+    assert memory_cache(0) > 0          # the destroyed plans' buffers were held for reuse
+    assert memory_cache(0) == 0
+    for o in outs:
+        assert_close(o, c_ref, "c128", "forward after reuse")
+    default_cap = torch.cuda.get_device_properties(0).total_memory // 4
+    try:
+        memory_cache(0, 0)
+        plan = _plan(p, "c128")
+        assert_close(plan.forward(y).cpu().numpy(), c_ref, "c128", "forward without caching")
+        del plan
+        assert memory_cache(0) == 0
+    finally:
+        memory_cache(0, default_cap)
