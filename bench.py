@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--bspline-sweeps", type=int, default=0, metavar="REPS",
                     help="also run the B-spline test function sweeps (settings of Tables 5.7 and 5.8) with REPS "
                          "seeds per row")
-    ap.add_argument("--bspline-max-N", type=int, default=64,
+    ap.add_argument("--bspline-max-N", type=int, default=256,
                     help="largest expansion N of the threshold-truncation rows")
     ap.add_argument("--emit-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="no GPU: turn the counter files of two rocprofv3 --pmc runs of this script "

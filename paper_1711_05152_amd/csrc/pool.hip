@@ -6,11 +6,12 @@
 // 50-110 ms, against a few ms of kernels per step).  Freed blocks are therefore kept mapped, per
 // device, in size classes and handed out again:
 //   * classes: powers of two up to 2 MiB; above, eight classes per octave rounded to 2 MiB (at most
-//     12.5 % slack);
+//     12.5 % slack); a request takes the smallest cached block of its class or of a class at most
+//     1.5 times larger (the sizes of consecutive sparse-FFT steps drift by tens of percent);
 //   * a freed block may still be read or written by work queued before the free (hipFree waited
 //     for the device, the cache does not), so it is "pending" until the next device-wide
-//     synchronisation; the cache synchronises only when a request finds no ready block of its
-//     class but a pending one;
+//     synchronisation; the cache synchronises only when a request finds no fitting ready block but
+//     a fitting pending one;
 //   * idle bytes per device are capped (default a quarter of the device's memory, see
 //     mr1l_memory_cache); a free beyond the cap goes back to the driver;
 //   * a hipMalloc that fails for lack of memory empties the device's cache and is retried once.
@@ -89,7 +90,7 @@ size_t trim_locked(int dev) {
 
 }  // namespace
 
-hipError_t pool_alloc(void** p, size_t bytes, int* dev_out) {
+hipError_t pool_alloc(void** p, size_t bytes, int* dev_out, size_t* block_out) {
     *p = nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -99,19 +100,25 @@ hipError_t pool_alloc(void** p, size_t bytes, int* dev_out) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         DevCache& C = cache_of(dev);
-        auto it = C.ready.find(c);
-        if (it == C.ready.end() && C.pending.count(c)) {
+        const size_t cmax = c + c / 2;
+        auto fit = [&](std::multimap<size_t, void*>& m) {
+            auto it = m.lower_bound(c);
+            return (it != m.end() && it->first <= cmax) ? it : m.end();
+        };
+        auto it = fit(C.ready);
+        if (it == C.ready.end() && fit(C.pending) != C.pending.end()) {
             // every pending block becomes reusable once the device has drained
             e = hipDeviceSynchronize();
             if (e != hipSuccess) return e;
             C.ready.insert(C.pending.begin(), C.pending.end());
             C.pending.clear();
-            it = C.ready.find(c);
+            it = fit(C.ready);
         }
         if (it != C.ready.end()) {
             *p = it->second;
+            *block_out = it->first;
+            C.idle -= it->first;
             C.ready.erase(it);
-            C.idle -= c;
             return hipSuccess;
         }
     }
@@ -125,12 +132,13 @@ hipError_t pool_alloc(void** p, size_t bytes, int* dev_out) {
         e = hipMalloc(p, c);
     }
     if (e != hipSuccess) *p = nullptr;
+    else *block_out = c;
     return e;
 }
 
-void pool_free(void* p, size_t bytes, int dev) {
+// c: the size of the block as handed out by pool_alloc
+void pool_free(void* p, size_t c, int dev) {
     if (!p) return;
-    const size_t c = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         DevCache& C = cache_of(dev);

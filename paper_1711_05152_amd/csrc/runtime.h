@@ -25,20 +25,21 @@ void clear_error();
     } while (0)
 
 // Caching device allocator (pool.hip): every DevMem goes through it.
-hipError_t pool_alloc(void** p, size_t bytes, int* dev);
-void pool_free(void* p, size_t bytes, int dev);
+hipError_t pool_alloc(void** p, size_t bytes, int* dev, size_t* block);
+void pool_free(void* p, size_t block, int dev);
 
 // Owning device allocation (size-classed, cached per device; see pool.hip).
 struct DevMem {
     void* p = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;    // requested
+    size_t block = 0;    // size of the cached block behind p (>= bytes)
     int dev = -1;
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
-    DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) {
+    DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes), block(o.block), dev(o.dev) {
         o.p = nullptr;
-        o.bytes = 0;
+        o.bytes = o.block = 0;
         o.dev = -1;
     }
     DevMem& operator=(DevMem&& o) noexcept {
@@ -46,24 +47,25 @@ struct DevMem {
             release();
             p = o.p;
             bytes = o.bytes;
+            block = o.block;
             dev = o.dev;
             o.p = nullptr;
-            o.bytes = 0;
+            o.bytes = o.block = 0;
             o.dev = -1;
         }
         return *this;
     }
     ~DevMem() { release(); }
     void release() {
-        if (p) pool_free(p, bytes, dev);
+        if (p) pool_free(p, block, dev);
         p = nullptr;
-        bytes = 0;
+        bytes = block = 0;
         dev = -1;
     }
     hipError_t alloc(size_t b) {
         release();
         if (b == 0) return hipSuccess;
-        hipError_t e = pool_alloc(&p, b, &dev);
+        hipError_t e = pool_alloc(&p, b, &dev, &block);
         if (e == hipSuccess) bytes = b;
         return e;
     }
