@@ -344,3 +344,13 @@ def test_component_order_recovers_planted_support():
         # listed lexicographically in the processing order
         keys = res.freqs[:, order]
         assert np.all(np.diff(np.lexsort(keys.T[::-1])) == 1)
+
+
+def test_decision_margin_by_hand():
+    # |v|^2 = 1, 0.25, 0.0625 against delta^2 = 0.36: the closest is 0.25 (distance 0.11)
+    v = np.array([1.0, 0.5j, -0.25])
+    assert abs(S.decision_margin(v, 0.6, 10) - 0.11 / 0.36) < 1e-12
+    # delta^2 = 0.01 leaves all three above; with s = 1 the cut between 1 and 0.25 is the closest
+    assert abs(S.decision_margin(v, 0.1, 1) - 0.75) < 1e-12
+    # exact tie at the cut
+    assert S.decision_margin(np.array([1.0, 1.0j, 0.1]), 0.01, 1) == 0.0
