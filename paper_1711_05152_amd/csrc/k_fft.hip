@@ -171,9 +171,25 @@ template <int ELEMS> struct Padded { static constexpr int v = ELEMS + (ELEMS >> 
 // are line-aligned, and the work area holds column n2 at position (n2 + rot) mod N2, so their
 // work-area accesses stay aligned as well; stage 2 undoes (forward) or applies (adjoint) the
 // rotation when it loads or stores a row.  rot_base is the sample pointer in elements mod 1024.
+// Tiles of stages 1 and 3 (column DFTs): 2^TLG elements = C columns of N1 = 2^LGN1 values, 16 per
+// thread.  The default 4096-element tile leaves C = 4096 / N1 columns, i.e. row segments shorter
+// than a 128-byte line once N1 > 256 (fp32) or N1 > 512 (fp64); such lengths take a tile of C =
+// 128 B / element columns instead, as far as LDS allows (2^14 fp32 / 2^13 fp64 elements, 148 KiB),
+// run by 1024 or 512 threads.  Stage 2 keeps 4096-element row tiles.
+template <typename T, int LGN>
+struct ColTile {
+    static constexpr int LGN1 = split_lgN1(LGN);
+    static constexpr int LINE_LG = sizeof(T) == 4 ? 4 : 3;        // log2(128 B / element)
+    static constexpr int MAX_LG = sizeof(T) == 4 ? 14 : 13;
+    static constexpr int WANT = LGN1 + LINE_LG;
+    static constexpr int TLG = WANT < kTileLg ? kTileLg : (WANT > MAX_LG ? MAX_LG : WANT);
+    static constexpr int LGC = TLG - LGN1, C = 1 << LGC;
+    static constexpr int NT = (1 << TLG) / 16;                     // threads: 16 values each
+};
+
 template <typename T, int LGN>
 struct Rot {
-    static constexpr int LGN1 = split_lgN1(LGN), C = 1 << (kTileLg - LGN1);
+    static constexpr int C = ColTile<T, LGN>::C;
     static constexpr int AL = C < (int)(128 / sizeof(cx<T>)) ? C : (int)(128 / sizeof(cx<T>));
     __device__ static int of(int rot_base, int64_t rhs, int64_t stride, int64_t samp_off) {
         return (int)(((int64_t)rot_base + rhs * stride + samp_off) & (AL - 1));
@@ -363,9 +379,9 @@ constexpr int kVals = (1 << kTileLg) / kThreads;   // values per thread (16)
 
 // butterfly u of this thread in a stage with 2^LGNB butterflies per sequence: (sequence b, index j).
 // BF: sequence index fastest across threads (column tiles), else j fastest (row tiles).
-template <int LGNB, int NSEQ, bool BF>
+template <int LGNB, int NSEQ, bool BF, int NT = kThreads>
 __device__ __forceinline__ void bfly(int u, int& b, int& j) {
-    const int g = threadIdx.x + u * kThreads;
+    const int g = threadIdx.x + u * NT;
     if constexpr (BF) {
         b = g & (NSEQ - 1);
         j = g / NSEQ;
@@ -376,7 +392,7 @@ __device__ __forceinline__ void bfly(int u, int& b, int& j) {
 }
 
 // twiddles and radix-2^LR DFTs of stage I on the registers
-template <typename T, int LGN, int NSEQ, int SIGN, bool REMF, int I, bool BF>
+template <typename T, int LGN, int NSEQ, int SIGN, bool REMF, int I, bool BF, int NT = kThreads>
 __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict__ tw) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNS = stage_lgns(LGN, I, REMF);
@@ -385,7 +401,7 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict_
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         int b, j;
-        bfly<LGNB, NSEQ, BF>(u, b, j);
+        bfly<LGNB, NSEQ, BF, NT>(u, b, j);
         cx<T>* x = v + u * R;
         if constexpr (LGNS > 0) {
             const int k = j & ((1 << LGNS) - 1);
@@ -415,7 +431,7 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict_
 }
 
 // outputs of stage I -> LDS
-template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF>
+template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF, int NT = kThreads>
 __device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNS = stage_lgns(LGN, I, REMF);
@@ -424,7 +440,7 @@ __device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         int b, j;
-        bfly<LGNB, NSEQ, BF>(u, b, j);
+        bfly<LGNB, NSEQ, BF, NT>(u, b, j);
         const int k = j & ((1 << LGNS) - 1);
         const int base = b * S + ((j - k) << LR) + k;
 #pragma unroll
@@ -433,7 +449,7 @@ __device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
 }
 
 // inputs of stage I <- LDS
-template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF>
+template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF, int NT = kThreads>
 __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNB = LGN - LR;
@@ -441,7 +457,7 @@ __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         int b, j;
-        bfly<LGNB, NSEQ, BF>(u, b, j);
+        bfly<LGNB, NSEQ, BF, NT>(u, b, j);
         const int base = b * S + j;
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u * R + r] = buf[pidx(base + (r << LGNB))];
@@ -450,18 +466,18 @@ __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
 
 // stages I..last; stage I's inputs are in v (mapping BF0 for I = 0, else j-fast); the last stage
 // uses mapping BFL.  On return v holds the last stage's outputs and all LDS reads are done.
-template <typename T, int LGN, int NSEQ, int S, int SIGN, bool REMF, bool BF0, bool BFL, int I = 0>
+template <typename T, int LGN, int NSEQ, int S, int SIGN, bool REMF, bool BF0, bool BFL, int NT = kThreads, int I = 0>
 __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __restrict__ tw) {
     constexpr int NS = n_stages(LGN);
     constexpr bool BFI = (I == NS - 1) ? BFL : (I == 0 ? BF0 : false);
-    stage_compute<T, LGN, NSEQ, SIGN, REMF, I, BFI>(v, tw);
+    stage_compute<T, LGN, NSEQ, SIGN, REMF, I, BFI, NT>(v, tw);
     if constexpr (I + 1 < NS) {
         constexpr bool BFN = (I + 1 == NS - 1) ? BFL : false;
-        stage_store<T, LGN, NSEQ, S, REMF, I, BFI>(buf, v);
+        stage_store<T, LGN, NSEQ, S, REMF, I, BFI, NT>(buf, v);
         __syncthreads();
-        stage_load<T, LGN, NSEQ, S, REMF, I + 1, BFN>(buf, v);
+        stage_load<T, LGN, NSEQ, S, REMF, I + 1, BFN, NT>(buf, v);
         __syncthreads();
-        fft_regs<T, LGN, NSEQ, S, SIGN, REMF, BF0, BFL, I + 1>(buf, v, tw);
+        fft_regs<T, LGN, NSEQ, S, SIGN, REMF, BF0, BFL, NT, I + 1>(buf, v, tw);
     }
 }
 
@@ -471,17 +487,19 @@ __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __re
 // 3: x = work (bins) * chirp where the alias bitmaps mark the bin as holding exactly one frequency,
 // else 0 (the adjoint's scatter writes only those bins).
 template <typename T, int LGN, int SRC>
-__global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict__ lat, const cx<T>* __restrict__ src,
-                                                 int64_t src_stride, cx<T>* work, int sign,
-                                                 const cx<T>* __restrict__ tw, int rot_base) {
-    constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
-    constexpr int LGC = kTileLg - LGN1, C = 1 << LGC, N1 = 1 << LGN1;
+__global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p1(TxArgs a, const int* __restrict__ lat,
+                                                            const cx<T>* __restrict__ src, int64_t src_stride,
+                                                            cx<T>* work, int sign, const cx<T>* __restrict__ tw,
+                                                            int rot_base) {
+    using CT = ColTile<T, LGN>;
+    constexpr int LGN1 = CT::LGN1, LGN2 = LGN - LGN1;
+    constexpr int LGC = CT::LGC, C = CT::C, N1 = 1 << LGN1, NT = CT::NT;
     constexpr int S = N1 + 1;
-    constexpr int TPL_LG = LGN - kTileLg;
+    constexpr int TPL_LG = LGN - CT::TLG;
     constexpr int NS = n_stages(LGN1);
     constexpr int LR0 = stage_lr(LGN1, 0, true), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
     constexpr int LRL = stage_lr(LGN1, NS - 1, true), RL = 1 << LRL, LGNBL = LGN1 - LRL;
-    __shared__ cx<T> lds[Padded<(1 << kTileLg) + C>::v];
+    __shared__ cx<T> lds[Padded<(1 << CT::TLG) + C>::v];
     __shared__ cx<T> ph[PhaseTab<T>::n];
     phase_fill<T>(ph);
     __syncthreads();
@@ -498,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int col, j;
-        bfly<LGNB0, C, true>(u, col, j);
+        bfly<LGNB0, C, true, NT>(u, col, j);
         const int n2 = (c0 + col - rot) & N2M;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
@@ -512,12 +530,12 @@ __global__ __launch_bounds__(kThreads) void k_p1(TxArgs a, const int* __restrict
             v[u * R0 + r] = x;
         }
     }
-    fft_regs<T, LGN1, C, S, -1, true, true, true>(lds, v, tw);
+    fft_regs<T, LGN1, C, S, -1, true, true, true, NT>(lds, v, tw);
     // outputs: column n2, k1 = j + r N1/RL; times w_N^{n2 k1}, stored at k1 N2 + (n2 + rot) mod N2
 #pragma unroll
     for (int u = 0; u < kVals / RL; ++u) {
         int col, j;
-        bfly<LGNBL, C, true>(u, col, j);
+        bfly<LGNBL, C, true, NT>(u, col, j);
         const int n2 = (c0 + col - rot) & N2M;
         cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
         const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNBL) & ((1 << LGN) - 1)), LGN, ph);
@@ -615,17 +633,19 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
 
 // ---- four-step stage 3 -----------------------------------------------------------------------------
 template <typename T, int LGN, bool TO_SAMPLES>
-__global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work, cx<T>* dst,
-                                                 int64_t dst_stride, int sign, int scale_by_invM,
-                                                 const cx<T>* __restrict__ tw, int rot_base) {
-    constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
-    constexpr int LGC = kTileLg - LGN1, C = 1 << LGC, N1 = 1 << LGN1;
+__global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work,
+                                                            cx<T>* dst, int64_t dst_stride, int sign,
+                                                            int scale_by_invM, const cx<T>* __restrict__ tw,
+                                                            int rot_base) {
+    using CT = ColTile<T, LGN>;
+    constexpr int LGN1 = CT::LGN1, LGN2 = LGN - LGN1;
+    constexpr int LGC = CT::LGC, C = CT::C, N1 = 1 << LGN1, NT = CT::NT;
     constexpr int S = N1 + 1;
-    constexpr int TPL_LG = LGN - kTileLg;
+    constexpr int TPL_LG = LGN - CT::TLG;
     constexpr int NS = n_stages(LGN1);
     constexpr int LR0 = stage_lr(LGN1, 0, false), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
     constexpr int LRL = stage_lr(LGN1, NS - 1, false), RL = 1 << LRL, LGNBL = LGN1 - LRL;
-    __shared__ cx<T> lds[Padded<(1 << kTileLg) + C>::v];
+    __shared__ cx<T> lds[Padded<(1 << CT::TLG) + C>::v];
     __shared__ cx<T> ph[PhaseTab<T>::n];
     phase_fill<T>(ph);
     __syncthreads();
@@ -640,7 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int col, j;
-        bfly<LGNB0, C, true>(u, col, j);
+        bfly<LGNB0, C, true, NT>(u, col, j);
         const int n2 = (c0 + col - rot) & N2M;
         cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
         const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNB0) & ((1 << LGN) - 1)), LGN, ph);
@@ -651,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
             wk = cmul(wk, ws);
         }
     }
-    fft_regs<T, LGN1, C, S, +1, false, true, true>(lds, v, tw);
+    fft_regs<T, LGN1, C, S, +1, false, true, true, NT>(lds, v, tw);
     cx<T>* out = TO_SAMPLES ? dst + rhs * dst_stride + D.samp_off : w;
     const T sc = scale_by_invM ? (T)D.invM : (T)1;
     // the inverse column DFTs read all of the tile before any thread writes (fft_regs ends with a
@@ -659,7 +679,7 @@ __global__ __launch_bounds__(kThreads) void k_p3(TxArgs a, const int* __restrict
 #pragma unroll
     for (int u = 0; u < kVals / RL; ++u) {
         int col, j;
-        bfly<LGNBL, C, true>(u, col, j);
+        bfly<LGNBL, C, true, NT>(u, col, j);
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int n1 = j + (r << LGNBL);
@@ -782,15 +802,16 @@ void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
     with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
         constexpr int lg = decltype(LG)::value;
+        using CT = ColTile<T, lg>;
+        const dim3 grid((unsigned)(g.nlat << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
         if (src_is_samples)
-            hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw, rb);
+            hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, rb);
         else if (mask_bins)
-            hipLaunchKernelGGL((k_p1<T, lg, 3>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
+            hipLaunchKernelGGL((k_p1<T, lg, 3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
         else
-            hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, dim3(kThreads), 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
+            hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
     });
 }
 
@@ -818,14 +839,15 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
     with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
         constexpr int lg = decltype(LG)::value;
+        using CT = ColTile<T, lg>;
+        const dim3 grid((unsigned)(g.nlat << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
         if (dst_is_samples)
-            hipLaunchKernelGGL((k_p3<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, dst, dst_stride, sign,
+            hipLaunchKernelGGL((k_p3<T, lg, true>), grid, block, 0, s, a, g.lat, work, dst, dst_stride, sign,
                                (int)scale_by_invM, tw, rb);
         else
-            hipLaunchKernelGGL((k_p3<T, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, work, dst, dst_stride,
+            hipLaunchKernelGGL((k_p3<T, lg, false>), grid, block, 0, s, a, g.lat, work, dst, dst_stride,
                                sign, (int)scale_by_invM, tw, 0);
     });
 }
@@ -877,7 +899,9 @@ hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cons
             const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), 1);
             with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
                 constexpr int lg = decltype(LG)::value;
-                hipLaunchKernelGGL((k_p1<double, lg, 2>), grid, dim3(kThreads), 0, s, a, g.lat,
+                using CT = ColTile<double, lg>;
+                const dim3 grid1((unsigned)(g.nlat << (lg - CT::TLG)), 1);
+                hipLaunchKernelGGL((k_p1<double, lg, 2>), grid1, dim3(CT::NT), 0, s, a, g.lat,
                                    (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw, 0);
                 hipLaunchKernelGGL((k_p2<double, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, tmp,
                                    (const cx<double>*)nullptr, -1, tw, -1, -1);

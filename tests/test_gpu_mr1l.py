@@ -267,3 +267,27 @@ def test_memory_cache_reuse_and_release():
         assert memory_cache(0) == 0
     finally:
         memory_cache(0, default_cap)
+
+
+LARGE = [
+    # Bluestein lengths 2^21 .. 2^23: stage-1/3 tiles of 8192 or 16384 elements (fp32) and of 8192
+    # elements (fp64) hold 128-byte row segments; 2^24 keeps shorter segments
+    ("lg21", 3000, 5, 30, 2, (1 << 19) + 1, 1 << 20),
+    ("lg22", 3000, 5, 30, 2, (1 << 20) + 1, 1 << 21),
+    ("lg23", 3000, 5, 30, 1, (1 << 21) + 1, 1 << 22),
+]
+
+
+@pytest.mark.parametrize("case", LARGE, ids=[c[0] for c in LARGE])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_large_bluestein_lengths(case, dtype):
+    torch = require_gpu()
+    name, n, d, box, L, mlo, mhi = case
+    p = transform_problem(rng_for(303, zlib.crc32(name.encode())), n, d, box, L, mlo, mhi, n_rhs=2)
+    print(f"large {name} {dtype} M={list(p.M)}", flush=True)
+    plan = _plan(p, dtype)
+    c = plan.forward(_to(torch, p.samples, dtype))
+    yy = plan.adjoint(_to(torch, p.coeffs, dtype))
+    torch.cuda.synchronize()
+    assert_close(c.cpu().numpy(), O.forward(p.freqs, p.M, p.z, p.samples, "paper"), dtype, f"forward {name}")
+    assert_close(yy.cpu().numpy(), O.adjoint(p.freqs, p.M, p.z, p.coeffs, "paper"), dtype, f"adjoint {name}")
