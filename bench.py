@@ -376,7 +376,7 @@ def extra_autograd(steps: int):
     right-hand sides, y = A c_true + complex Gaussian noise sigma = 1e-3, complex64."""
     import numpy as np
     import torch
-    from paper_1711_05152_amd.autograd import Mr1lSynth
+    from paper_1711_05152_amd.autograd import Mr1lSynth, WeightedLsq
     from paper_1711_05152_amd.mr1l import Plan
     from workloads import lsq_c5
     freqs, M, z, seed = lsq_c5()
@@ -391,13 +391,12 @@ def extra_autograd(steps: int):
         res, _, _ = ep.alias()
         step = 1.0 / sum(int(torch.bincount(res[l]).max()) for l in range(ep.L))
         del res
-    w = torch.from_numpy(np.concatenate([np.full(int(m), 1.0 / m) for m in M]).astype(np.float32)).to("cuda:0")
     c = torch.zeros((n_rhs, ep.n), dtype=torch.complex64, device="cuda:0", requires_grad=True)
     losses = []
 
     def gd_step():
-        r = Mr1lSynth.apply(c, ep) - y
-        loss = 0.5 * (w * (r.real ** 2 + r.imag ** 2)).sum()
+        # fused residual, loss and loss gradient (one library pass over the samples each way)
+        loss = WeightedLsq.apply(Mr1lSynth.apply(c, ep), y, ep)
         c.grad = None
         loss.backward()
         with torch.no_grad():

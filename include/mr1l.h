@@ -121,6 +121,21 @@ mr1l_status mr1l_alias(mr1l_plan_t plan, int64_t* residues, uint8_t* unaliased, 
 mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_uncovered,
                       int64_t* fft_lengths);
 
+/* Weighted least-squares residual on the plan's stacked lattices: for samples s = A c (the
+ * Fourier matrix of Sec. 2.1, a plan with weights MR1L_W_EVAL) and data y,
+ *     loss = 1/2 sum_rhs sum_l (1/M_l) sum_j |s_l[j] - y_l[j]|^2
+ *     grad = scale * (1/M_l) (s_l[j] - y_l[j])      (gradient of loss with respect to s)
+ * computed in one pass over s and y (any weighting of the plan; only its lattice sizes are used).
+ *   s, y    device [n_rhs][sum_l M_l] complex of the plan's dtype (read only; grad may alias s)
+ *   scale   optional device double [1] multiplying grad (NULL: 1)
+ *   grad    optional device [n_rhs][sum_l M_l] complex (written)
+ *   loss    optional device double [1] (written; summed in double in a fixed order)
+ * Asynchronous on ``stream``; the first call with a loss allocates the plan's buffer of block
+ * partials (64 L n_rhs doubles), later calls allocate nothing.  Errors: MR1L_ERR_ARG for a NULL
+ * plan or NULL s / y with samples present. */
+mr1l_status mr1l_lsq_residual(mr1l_plan_t plan, const void* s, const void* y, const double* scale, void* grad,
+                              double* loss, void* stream);
+
 /* Plan-cached index work.  The residues r_l(k) and the alias bitmaps of Alg. 2 depend only on I
  * and the lattices, not on the samples or coefficients.  By default every forward and adjoint call
  * recomputes them (Alg. 2 as stated).  With enable = 1 the next call computes them once and later

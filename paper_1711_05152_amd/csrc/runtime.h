@@ -149,6 +149,7 @@ struct Plan {
     int64_t filt_total = 0;
     int64_t bm_total = 0;
     DevMem freqs, desc, tx, tx_foff, z, z32, bitmaps, filt, work, grp_lat, res32, hist, rtiles, part, bcnt, bloc, bbase, perm;
+    DevMem lsq_part;                   // block partials of mr1l_lsq_residual (allocated on first use)
     std::vector<FftGroup> groups;   // lattices grouped by Bluestein length
     void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};

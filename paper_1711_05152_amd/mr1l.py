@@ -110,6 +110,22 @@ class Plan:
         check(lib().mr1l_adjoint(self._h, _ptr(c), _ptr(y), _stream(self.device)), "mr1l_adjoint")
         return y
 
+    def lsq_residual(self, s: torch.Tensor, y: torch.Tensor, grad: torch.Tensor | None = None,
+                     loss: torch.Tensor | None = None, scale: torch.Tensor | None = None) -> None:
+        """mr1l_lsq_residual: loss = 1/2 sum (1/M_l) |s - y|^2 into ``loss`` (float64 scalar tensor)
+        and/or grad = scale (1/M_l)(s - y) into ``grad`` (may be ``s``); ``scale`` a float64
+        scalar tensor on the device (None: 1)."""
+        s = self._check_tensor(s, self.sum_M, "s")
+        y = self._check_tensor(y, self.sum_M, "y")
+        if grad is not None:
+            grad = self._check_tensor(grad, self.sum_M, "grad")
+        for t, name in ((loss, "loss"), (scale, "scale")):
+            if t is not None and (t.dtype != torch.float64 or t.numel() != 1 or t.device != s.device
+                                  or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 scalar tensor on the plan's device")
+        check(lib().mr1l_lsq_residual(self._h, _ptr(s), _ptr(y), _ptr(scale), _ptr(grad), _ptr(loss),
+                                      _stream(self.device)), "mr1l_lsq_residual")
+
     def alias(self):
         """mr1l_alias: (residues int64 [L, n], unaliased uint8 [L, n], counter uint8 [n]) on device."""
         res = torch.empty((self.max_nlat, self.n), dtype=torch.int64, device=self.device)

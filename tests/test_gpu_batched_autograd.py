@@ -164,3 +164,35 @@ def test_gradient_descent_decreases_loss():
             c -= step * c.grad
     assert all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:])), losses
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_fused_lsq_loss_and_gradient():
+    """WeightedLsq (one library pass each way) gives the loss 1/2 sum_l (1/M_l)||s_l - y_l||^2 and
+    the gradient of the elementwise autograd formulation; composed with Mr1lSynth it reproduces the
+    dense FP64 gradient A^H W (A c - y); the in-place gradient (grad = s) and the scale work."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.autograd import Mr1lSynth, WeightedLsq
+    from paper_1711_05152_amd.mr1l import Plan
+    p = transform_problem(rng_for(505), 300, 12, 16, 5, 300, 700, n_rhs=3)
+    A = np.concatenate([O.fourier_matrix(O.lattice_nodes(p.z[l], p.M[l]), p.freqs) for l in range(len(p.M))])
+    wv = np.concatenate([np.full(m, 1.0 / m) for m in p.M])
+    for dtype in ("c128", "c64"):
+        ep = Plan(p.freqs, p.M, p.z, dtype=dtype, weights="eval", n_rhs=3, device=0)
+        y = _t(torch, p.samples, dtype)
+        s_np = cn01(rng_for(506), p.samples.shape)
+        s = _t(torch, s_np, dtype).requires_grad_(True)
+        loss = WeightedLsq.apply(s, y, ep)
+        ref_loss = 0.5 * float(np.sum(wv[None, :] * np.abs(s_np - p.samples) ** 2))
+        assert abs(loss.item() - ref_loss) <= (1e-13 if dtype == "c128" else 1e-6) * ref_loss
+        (3.0 * loss).backward()
+        ref_grad = 3.0 * wv[None, :] * (s_np - p.samples)
+        assert_close(s.grad.cpu().numpy(), ref_grad, dtype, f"fused lsq grad {dtype}")
+        # in place, with a device scale
+        g = s.detach().clone()
+        ep.lsq_residual(g, y, grad=g, scale=torch.tensor(2.0, dtype=torch.float64, device="cuda:0"))
+        assert_close(g.cpu().numpy(), 2.0 * wv[None, :] * (s_np - p.samples), dtype, f"in-place grad {dtype}")
+        # through the synthesis: gradient with respect to c
+        c = _t(torch, p.coeffs, dtype).requires_grad_(True)
+        WeightedLsq.apply(Mr1lSynth.apply(c, ep), y, ep).backward()
+        ref = (A.conj().T @ (wv[:, None] * (A @ p.coeffs.T - p.samples.T))).T
+        assert_close(c.grad.detach().cpu().numpy(), ref, dtype, f"composed lsq grad {dtype}")
