@@ -344,6 +344,104 @@ __global__ __launch_bounds__(256) void k_gather(TxArgs a, const cx<T>* __restric
     }
 }
 
+// Single right-hand side: kSplit lanes per frequency share its lattice slots (lane s takes slots
+// s, s + kSplit, ...), so eight times as many threads keep the random residue, bitmap and bin
+// accesses in flight.  The gather's lane 0 adds the values in ascending slot order, fetching them
+// from the other lanes by shuffles: the same order and rounding as one thread walking all slots.
+constexpr int kSplit = 8;
+constexpr int kSplitSlots = 2;   // slots per lane per pass (16 lattice slots of a frequency)
+
+// loads of the residues and alias words of slots j0 + u kSplit + sub (clamped to the last slot)
+__device__ __forceinline__ void split_slots(const TxArgs& a, const TxDesc& t, int j0, int sub, int64_t g,
+                                            int32_t* r, uint32_t* w) {
+#pragma unroll
+    for (int u = 0; u < kSplitSlots; ++u) r[u] = a.res32[(int64_t)min(j0 + u * kSplit + sub, t.nlat - 1) * a.rs + g];
+#pragma unroll
+    for (int u = 0; u < kSplitSlots; ++u) {
+        const LatDesc& D = a.desc[t.lat0 + min(j0 + u * kSplit + sub, t.nlat - 1)];
+        w[u] = a.bitmaps[D.bm_off + D.bm_words + (r[u] >> 5)];
+    }
+}
+
+template <typename T, bool SINGLE>
+__global__ __launch_bounds__(256) void k_gather_split(TxArgs a, const cx<T>* __restrict__ work,
+                                                      cx<T>* coeffs) {
+    const int sub = threadIdx.x & (kSplit - 1);
+    const int lead = (int)(threadIdx.x & 63) & ~(kSplit - 1);      // lane of sub 0 in the wave
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / kSplit;
+    for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSplit; g < a.n; g += stride) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        cx<T> acc = {(T)0, (T)0};
+        int cnt = 0;
+        for (int j0 = 0; j0 < t.nlat; j0 += kSplit * kSplitSlots) {
+            int32_t r[kSplitSlots];
+            uint32_t w[kSplitSlots];
+            split_slots(a, t, j0, sub, g, r, w);
+            cx<T> v[kSplitSlots];
+            int own[kSplitSlots];
+#pragma unroll
+            for (int u = 0; u < kSplitSlots; ++u) {
+                const int j = j0 + u * kSplit + sub;
+                own[u] = j < t.nlat && !((w[u] >> (r[u] & 31)) & 1u);
+                v[u] = own[u] ? work[a.desc[t.lat0 + j].work_off + r[u]] : cx<T>{(T)0, (T)0};
+            }
+#pragma unroll
+            for (int u = 0; u < kSplitSlots; ++u) {
+#pragma unroll
+                for (int q = 0; q < kSplit; ++q) {   // slot j0 + u kSplit + q, ascending
+                    const T vx = __shfl(v[u].x, lead + q);
+                    const T vy = __shfl(v[u].y, lead + q);
+                    const int o = __shfl(own[u], lead + q);
+                    if (o) {
+                        acc = acc + cx<T>{vx, vy};
+                        ++cnt;
+                    }
+                }
+            }
+        }
+        if (sub == 0) coeffs[g] = cnt ? cx<T>{acc.x / (T)cnt, acc.y / (T)cnt} : cx<T>{(T)0, (T)0};
+    }
+}
+
+template <typename T, bool SINGLE>
+__global__ __launch_bounds__(256) void k_scatter_split(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
+    constexpr int SPAN = kSplit * kSplitSlots;
+    const int sub = threadIdx.x & (kSplit - 1);
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / kSplit;
+    for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSplit; g < a.n; g += stride) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        if (t.nlat == 0) continue;
+        const cx<T> c = coeffs[g];
+        // counter_k over all slots (the first pass's slots are kept for the writes)
+        int32_t r[kSplitSlots];
+        uint32_t w[kSplitSlots];
+        split_slots(a, t, 0, sub, g, r, w);
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kSplitSlots; ++u) cnt += (u * kSplit + sub < t.nlat) && !((w[u] >> (r[u] & 31)) & 1u);
+        for (int j0 = SPAN; j0 < t.nlat; j0 += SPAN) {
+            int32_t rx[kSplitSlots];
+            uint32_t wx[kSplitSlots];
+            split_slots(a, t, j0, sub, g, rx, wx);
+#pragma unroll
+            for (int u = 0; u < kSplitSlots; ++u)
+                cnt += (j0 + u * kSplit + sub < t.nlat) && !((wx[u] >> (rx[u] & 31)) & 1u);
+        }
+#pragma unroll
+        for (int m = 1; m < kSplit; m <<= 1) cnt += __shfl_xor(cnt, m);
+        if (cnt == 0) continue;
+        const cx<T> v = {c.x / (T)cnt, c.y / (T)cnt};
+        for (int j0 = 0; j0 < t.nlat; j0 += SPAN) {
+            if (j0 > 0) split_slots(a, t, j0, sub, g, r, w);
+#pragma unroll
+            for (int u = 0; u < kSplitSlots; ++u) {
+                const int j = j0 + u * kSplit + sub;
+                if (j < t.nlat && !((w[u] >> (r[u] & 31)) & 1u)) work[a.desc[t.lat0 + j].work_off + r[u]] = v;
+            }
+        }
+    }
+}
+
 // zero the first M_l entries (the DFT bins) of every lattice's work region (Fourier-matrix
 // adjoint, which accumulates into the bins)
 template <typename T>
@@ -646,6 +744,11 @@ void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval,
         const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
         if (eval && single) hipLaunchKernelGGL((k_gather<T, true, true, RB>), grid, dim3(256), 0, s, a, work, coeffs);
         else if (eval) hipLaunchKernelGGL((k_gather<T, true, false, RB>), grid, dim3(256), 0, s, a, work, coeffs);
+        else if (RB == 1) {
+            const dim3 g4(grid_for(a.n * kSplit));
+            if (single) hipLaunchKernelGGL((k_gather_split<T, true>), g4, dim3(256), 0, s, a, work, coeffs);
+            else hipLaunchKernelGGL((k_gather_split<T, false>), g4, dim3(256), 0, s, a, work, coeffs);
+        }
         else if (single) hipLaunchKernelGGL((k_gather<T, false, true, RB>), grid, dim3(256), 0, s, a, work, coeffs);
         else hipLaunchKernelGGL((k_gather<T, false, false, RB>), grid, dim3(256), 0, s, a, work, coeffs);
     };
@@ -668,6 +771,11 @@ void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval
         const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
         if (eval && single) hipLaunchKernelGGL((k_scatter_eval<T, true, RB>), grid, dim3(256), 0, s, a, coeffs, work);
         else if (eval) hipLaunchKernelGGL((k_scatter_eval<T, false, RB>), grid, dim3(256), 0, s, a, coeffs, work);
+        else if (RB == 1) {
+            const dim3 g4(grid_for(a.n * kSplit));
+            if (single) hipLaunchKernelGGL((k_scatter_split<T, true>), g4, dim3(256), 0, s, a, coeffs, work);
+            else hipLaunchKernelGGL((k_scatter_split<T, false>), g4, dim3(256), 0, s, a, coeffs, work);
+        }
         else if (single) hipLaunchKernelGGL((k_scatter<T, true, RB>), grid, dim3(256), 0, s, a, coeffs, work);
         else hipLaunchKernelGGL((k_scatter<T, false, RB>), grid, dim3(256), 0, s, a, coeffs, work);
     };
