@@ -530,6 +530,14 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom), "avg_launch_ms": dom_ms,
                 "work_per_launch": nbytes}
 
+    # measured memory traffic (stored counter file of these sources) over each stage's launch time
+    kernel_traffic = {}
+    for k, t_ms in per_launch.items():
+        b = stored_traffic(k)
+        if b is not None:
+            kernel_traffic[k] = {"bytes_per_launch": b, "GBs": b / (t_ms * 1e-3) / 1e9,
+                                 "frac_hbm_peak": b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
     # end-to-end algorithmic bytes (samples + packed frequencies + coefficients, both directions)
     alg_bytes = 2 * (8 * sumM + n * d * 1 + 8 * n)
     e2e = {"alg_bytes_per_step": alg_bytes, "GBs": alg_bytes / (ms_event * 1e-3) / 1e9,
@@ -588,6 +596,7 @@ def main():
         "end_to_end": e2e,
         "stages_ms_per_step": per_step,
         "stages_ms_per_launch": per_launch,
+        "stages_measured_traffic": kernel_traffic or None,
         "cpu_baseline": cpu,
     }
     if not args.no_extras:
