@@ -144,6 +144,15 @@ mr1l_status mr1l_lsq_residual(mr1l_plan_t plan, const void* s, const void* y, co
  * Errors: MR1L_ERR_ARG for a NULL plan. */
 mr1l_status mr1l_cache_alias(mr1l_plan_t plan, int enable);
 
+/* Four-step schedule of the Bluestein FFTs.  A prime-length DFT runs as a power-of-two FFT of
+ * length 2^lgN split as 2^lgN1 columns by 2^(lgN - lgN1) rows; every length from 2^13 to 2^24 has
+ * the rule's split and its neighbours compiled, and the built-in table (measured on MI355X by
+ * paper_1711_05152_amd/tune_fft.py) picks one.  This call sets the split plans of ``dtype`` use
+ * for 2^lgN from now on (lgN1 > 0), restores the table's choice (lgN1 < 0) or only queries
+ * (lgN1 = 0); ``current`` (optional) receives the split in effect.  Plans read the schedule when
+ * they are created.  Errors: MR1L_ERR_ARG for a length outside 13..24 or a split not compiled. */
+mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current);
+
 /* Device-memory cache.  Every device buffer of the library (plan work areas, sparse-FFT steps)
  * comes from a per-device cache of size-classed blocks: a released block stays mapped and serves
  * later requests of its class, because allocating and freeing multi-GB regions through the driver

@@ -107,9 +107,22 @@ __host__ __device__ constexpr int split_lgN1(int lgN) {
                : ((lgN / 2) < (kTileLg - 4) ? (lgN / 2) : (kTileLg - 4));
 }
 
+// Splits compiled for each length: the rule above and its neighbours lgN1 - 1 and lgN1 + 1 where
+// both factors have 2^4 .. 2^12 points (stage-2 rows fit one tile).  Plans take the split of
+// their Bluestein lengths from the measured schedule table (fft_schedule.hip, mr1l_fft_split).
+__host__ __device__ constexpr bool split_ok(int lgN, int lgN1) {
+    return lgN1 >= 4 && lgN - lgN1 >= 4 && lgN1 <= kTileLg && lgN - lgN1 <= kTileLg;
+}
+__host__ __device__ constexpr bool split_compiled(int lgN, int lgN1) {
+    return lgN > kSmallMaxLg && lgN <= kMaxLgN && split_ok(lgN, lgN1) && lgN1 >= split_lgN1(lgN) - 1 &&
+           lgN1 <= split_lgN1(lgN) + 1;
+}
+int fft_split(int dtype, int lgN);   // split plans of this dtype use for Bluestein length 2^lgN
+
 // Lattices sharing one Bluestein length, launched together with kernels specialised for it.
 struct FftGroup {
     int lgN;
+    int lg1;          // four-step split 2^lgN = 2^lg1 * 2^(lgN - lg1) (0 on the one-block path)
     int small;        // one-block path (lgN <= kSmallMaxLg)
     int nlat;
     const int* lat;   // device [nlat] lattice indices

@@ -1,0 +1,58 @@
+// Schedule of the four-step Bluestein FFT: which compiled split each length uses.  The built-in
+// table is the one the tuning script measured (fft_schedule_table.h); mr1l_fft_split overrides an
+// entry for the process (the tuner itself times every candidate that way).  Plans read the
+// schedule when they are created.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+
+#include "common.h"
+#include "fft_schedule_table.h"
+#include "runtime.h"
+
+namespace mr1l {
+namespace {
+std::atomic<int> g_override[2][kMaxLgN + 1];
+struct InitOverrides {
+    InitOverrides() {
+        for (auto& row : g_override)
+            for (auto& v : row) v.store(-1);
+    }
+} g_init_overrides;
+
+int table_split(int dt, int lgN) {
+    const int t = kTunedSplit[dt][lgN];
+    return split_compiled(lgN, t) ? t : split_lgN1(lgN);
+}
+}  // namespace
+
+int fft_split(int dtype, int lgN) {
+    const int dt = dtype == MR1L_C128 ? 1 : 0;
+    if (lgN <= kSmallMaxLg || lgN > kMaxLgN) return split_lgN1(lgN);
+    const int o = g_override[dt][lgN].load();
+    return o >= 0 ? o : table_split(dt, lgN);
+}
+
+}  // namespace mr1l
+
+using namespace mr1l;
+
+extern "C" mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current) {
+    clear_error();
+    if ((dtype != MR1L_C64 && dtype != MR1L_C128) || lgN <= kSmallMaxLg || lgN > kMaxLgN) {
+        set_error("mr1l_fft_split: dtype or length outside the four-step range 2^13 .. 2^24");
+        return MR1L_ERR_ARG;
+    }
+    const int dt = dtype == MR1L_C128 ? 1 : 0;
+    if (lgN1 > 0) {
+        if (!split_compiled(lgN, lgN1)) {
+            set_error("mr1l_fft_split: split not compiled for this length (rule +- 1, factors 2^4 .. 2^12)");
+            return MR1L_ERR_ARG;
+        }
+        g_override[dt][lgN].store(lgN1);
+    } else if (lgN1 < 0) {
+        g_override[dt][lgN].store(-1);
+    }
+    if (current) *current = fft_split(dtype, lgN);
+    return MR1L_OK;
+}

@@ -176,9 +176,9 @@ template <int ELEMS> struct Padded { static constexpr int v = ELEMS + (ELEMS >> 
 // than a 128-byte line once N1 > 256 (fp32) or N1 > 512 (fp64); such lengths take a tile of C =
 // 128 B / element columns instead, as far as LDS allows (2^14 fp32 / 2^13 fp64 elements, 148 KiB),
 // run by 1024 or 512 threads.  Stage 2 keeps 4096-element row tiles.
-template <typename T, int LGN>
+template <typename T, int LGN, int LG1>
 struct ColTile {
-    static constexpr int LGN1 = split_lgN1(LGN);
+    static constexpr int LGN1 = LG1;
     static constexpr int LINE_LG = sizeof(T) == 4 ? 4 : 3;        // log2(128 B / element)
     static constexpr int MAX_LG = sizeof(T) == 4 ? 14 : 13;
     static constexpr int WANT = LGN1 + LINE_LG;
@@ -187,9 +187,9 @@ struct ColTile {
     static constexpr int NT = (1 << TLG) / 16;                     // threads: 16 values each
 };
 
-template <typename T, int LGN>
+template <typename T, int LGN, int LG1>
 struct Rot {
-    static constexpr int C = ColTile<T, LGN>::C;
+    static constexpr int C = ColTile<T, LGN, LG1>::C;
     static constexpr int AL = C < (int)(128 / sizeof(cx<T>)) ? C : (int)(128 / sizeof(cx<T>));
     __device__ static int of(int rot_base, int64_t rhs, int64_t stride, int64_t samp_off) {
         return (int)(((int64_t)rot_base + rhs * stride + samp_off) & (AL - 1));
@@ -486,12 +486,12 @@ __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __re
 // SRC 0: x = samples * chirp, 1: x = work (bins) * chirp, 2: x = work as is (all N entries),
 // 3: x = work (bins) * chirp where the alias bitmaps mark the bin as holding exactly one frequency,
 // else 0 (the adjoint's scatter writes only those bins).
-template <typename T, int LGN, int SRC>
-__global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p1(TxArgs a, const int* __restrict__ lat,
+template <typename T, int LGN, int LG1, int SRC>
+__global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, const int* __restrict__ lat,
                                                             const cx<T>* __restrict__ src, int64_t src_stride,
                                                             cx<T>* work, int sign, const cx<T>* __restrict__ tw,
                                                             int rot_base) {
-    using CT = ColTile<T, LGN>;
+    using CT = ColTile<T, LGN, LG1>;
     constexpr int LGN1 = CT::LGN1, LGN2 = LGN - LGN1;
     constexpr int LGC = CT::LGC, C = CT::C, N1 = 1 << LGN1, NT = CT::NT;
     constexpr int S = N1 + 1;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p1(TxArgs a, const in
     const cx<T>* in = src + rhs * src_stride + (SRC == 0 ? D.samp_off : D.work_off);
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
     const int64_t nvalid = (SRC == 2) ? ((int64_t)1 << LGN) : D.M;
-    const int rot = SRC == 0 ? Rot<T, LGN>::of(rot_base, rhs, src_stride, D.samp_off) : 0;
+    const int rot = SRC == 0 ? Rot<T, LGN, LG1>::of(rot_base, rhs, src_stride, D.samp_off) : 0;
     constexpr int N2M = (1 << LGN2) - 1;
     cx<T> v[kVals];
 #pragma unroll
@@ -552,11 +552,11 @@ __global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p1(TxArgs a, const in
 // One tile = 2^(12 - LGN2) rows.  CONV: row DFT, multiply by the filter (conjugated for sign +1),
 // inverse row DFT (the forward's last stage and the inverse's first stage have the same radix and
 // hold the same elements, so the product never leaves the registers); else row DFT only.
-template <typename T, int LGN, bool CONV>
+template <typename T, int LGN, int LG1, bool CONV>
 __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
                                                  const cx<T>* __restrict__ filt, int sign,
                                                  const cx<T>* __restrict__ tw, int rot_in_base, int rot_out_base) {
-    constexpr int LGN1 = split_lgN1(LGN), LGN2 = LGN - LGN1;
+    constexpr int LGN1 = LG1, LGN2 = LGN - LGN1;
     constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
     constexpr int TPL_LG = LGN - kTileLg;
     constexpr int LR0 = stage_lr(LGN2, 0, true), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
@@ -572,8 +572,8 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
     // rotation of the rows as stored by stage 1 / as stage 3 reads them (rot_*_base < 0: none)
-    const int rin = rot_in_base < 0 ? 0 : Rot<T, LGN>::of(rot_in_base, rhs, a.samp_stride, D.samp_off);
-    const int rout = rot_out_base < 0 ? 0 : Rot<T, LGN>::of(rot_out_base, rhs, a.samp_stride, D.samp_off);
+    const int rin = rot_in_base < 0 ? 0 : Rot<T, LGN, LG1>::of(rot_in_base, rhs, a.samp_stride, D.samp_off);
+    const int rout = rot_out_base < 0 ? 0 : Rot<T, LGN, LG1>::of(rot_out_base, rhs, a.samp_stride, D.samp_off);
     // Rows of the tile: ROWS/2 mirror pairs (p, N1 - p) of the [k1][k2] layout, pair 0 being
     // (0, N1/2).  The filter spectrum is even (B[k] = B[N - k]), i.e. B[k1][k2] = B[N1-k1][N2-1-k2]
     // for 0 < k1 < N1, so the second row of a pair reads its partner's filter values (the same
@@ -632,12 +632,12 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
 }
 
 // ---- four-step stage 3 -----------------------------------------------------------------------------
-template <typename T, int LGN, bool TO_SAMPLES>
-__global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work,
+template <typename T, int LGN, int LG1, bool TO_SAMPLES>
+__global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work,
                                                             cx<T>* dst, int64_t dst_stride, int sign,
                                                             int scale_by_invM, const cx<T>* __restrict__ tw,
                                                             int rot_base) {
-    using CT = ColTile<T, LGN>;
+    using CT = ColTile<T, LGN, LG1>;
     constexpr int LGN1 = CT::LGN1, LGN2 = LGN - LGN1;
     constexpr int LGC = CT::LGC, C = CT::C, N1 = 1 << LGN1, NT = CT::NT;
     constexpr int S = N1 + 1;
@@ -654,7 +654,7 @@ __global__ __launch_bounds__((ColTile<T, LGN>::NT)) void k_p3(TxArgs a, const in
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
-    const int rot = TO_SAMPLES ? Rot<T, LGN>::of(rot_base, rhs, dst_stride, D.samp_off) : 0;
+    const int rot = TO_SAMPLES ? Rot<T, LGN, LG1>::of(rot_base, rhs, dst_stride, D.samp_off) : 0;
     constexpr int N2M = (1 << LGN2) - 1;
     cx<T> v[kVals];
 #pragma unroll
@@ -774,6 +774,21 @@ static void with_lg(int lg, F&& f) {
     }
 }
 
+// four-step kernels for (2^lgN, split lg1): f(LG, LG1) with both as integral constants; lg1 must
+// be a compiled split (split_compiled), which plans guarantee
+template <typename F>
+static void with_split(int lgN, int lg1, F&& f) {
+    with_lg<kSmallMaxLg + 1, kMaxLgN>(lgN, [&](auto LG) {
+        constexpr int lg = decltype(LG)::value;
+        constexpr int r = split_lgN1(lg);
+        if (lg1 == r) f(LG, std::integral_constant<int, r>{});
+        if constexpr (split_compiled(lg, r - 1))
+            if (lg1 == r - 1) f(LG, std::integral_constant<int, r - 1>{});
+        if constexpr (split_compiled(lg, r + 1))
+            if (lg1 == r + 1) f(LG, std::integral_constant<int, r + 1>{});
+    });
+}
+
 template <typename T>
 void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride,
                             bool src_is_samples, cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
@@ -802,16 +817,16 @@ void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
-        constexpr int lg = decltype(LG)::value;
-        using CT = ColTile<T, lg>;
+    with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
+        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+        using CT = ColTile<T, lg, l1>;
         const dim3 grid((unsigned)(g.nlat << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
         if (src_is_samples)
-            hipLaunchKernelGGL((k_p1<T, lg, 0>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, rb);
+            hipLaunchKernelGGL((k_p1<T, lg, l1, 0>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, rb);
         else if (mask_bins)
-            hipLaunchKernelGGL((k_p1<T, lg, 3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
+            hipLaunchKernelGGL((k_p1<T, lg, l1, 3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
         else
-            hipLaunchKernelGGL((k_p1<T, lg, 1>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
+            hipLaunchKernelGGL((k_p1<T, lg, l1, 1>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
     });
 }
 
@@ -825,9 +840,10 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
     const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
-    with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
-        constexpr int lg = decltype(LG)::value;
-        hipLaunchKernelGGL((k_p2<T, lg, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, filt, sign, tw, ri, ro);
+    with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
+        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+        hipLaunchKernelGGL((k_p2<T, lg, l1, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, filt, sign, tw, ri,
+                           ro);
     });
 }
 
@@ -839,15 +855,15 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
-        constexpr int lg = decltype(LG)::value;
-        using CT = ColTile<T, lg>;
+    with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
+        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+        using CT = ColTile<T, lg, l1>;
         const dim3 grid((unsigned)(g.nlat << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
         if (dst_is_samples)
-            hipLaunchKernelGGL((k_p3<T, lg, true>), grid, block, 0, s, a, g.lat, work, dst, dst_stride, sign,
+            hipLaunchKernelGGL((k_p3<T, lg, l1, true>), grid, block, 0, s, a, g.lat, work, dst, dst_stride, sign,
                                (int)scale_by_invM, tw, rb);
         else
-            hipLaunchKernelGGL((k_p3<T, lg, false>), grid, block, 0, s, a, g.lat, work, dst, dst_stride,
+            hipLaunchKernelGGL((k_p3<T, lg, l1, false>), grid, block, 0, s, a, g.lat, work, dst, dst_stride,
                                sign, (int)scale_by_invM, tw, 0);
     });
 }
@@ -897,13 +913,13 @@ hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cons
             });
         } else {
             const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), 1);
-            with_lg<kSmallMaxLg + 1, kMaxLgN>(g.lgN, [&](auto LG) {
-                constexpr int lg = decltype(LG)::value;
-                using CT = ColTile<double, lg>;
+            with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
+                constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+                using CT = ColTile<double, lg, l1>;
                 const dim3 grid1((unsigned)(g.nlat << (lg - CT::TLG)), 1);
-                hipLaunchKernelGGL((k_p1<double, lg, 2>), grid1, dim3(CT::NT), 0, s, a, g.lat,
+                hipLaunchKernelGGL((k_p1<double, lg, l1, 2>), grid1, dim3(CT::NT), 0, s, a, g.lat,
                                    (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw, 0);
-                hipLaunchKernelGGL((k_p2<double, lg, false>), grid, dim3(kThreads), 0, s, a, g.lat, tmp,
+                hipLaunchKernelGGL((k_p2<double, lg, l1, false>), grid, dim3(kThreads), 0, s, a, g.lat, tmp,
                                    (const cx<double>*)nullptr, -1, tw, -1, -1);
             });
         }

@@ -157,7 +157,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->samp_off[l + 1] = P->samp_off[l] + D.M;
         D.lgN = ceil_lg(2 * D.M - 1);
         D.small = D.lgN <= kSmallMaxLg;
-        D.lgN1 = D.small ? 0 : split_lgN1(D.lgN);
+        D.lgN1 = D.small ? 0 : fft_split(sp.dtype, D.lgN);
         D.lgN2 = D.lgN - D.lgN1;
         D.work_off = woff;
         D.filt_off = woff;
@@ -204,6 +204,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             FftGroup g;
             g.lgN = spans[i].first;
             g.small = g.lgN <= kSmallMaxLg;
+            g.lg1 = P->hdesc[by_len[g.lgN][0]].lgN1;
             g.nlat = (int)by_len[g.lgN].size();
             g.lat = P->grp_lat.as<int>() + spans[i].second;
             P->groups.push_back(g);
@@ -273,9 +274,10 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     const Plan* sh = sp.share_filters;
     if (sh) {
         bool same = sh->dtype == sp.dtype && sh->L == L;
-        for (int l = 0; same && l < L; ++l) same = sh->hdesc[l].M == P->hdesc[l].M;
+        for (int l = 0; same && l < L; ++l)
+            same = sh->hdesc[l].M == P->hdesc[l].M && sh->hdesc[l].lgN1 == P->hdesc[l].lgN1;
         if (!same) {
-            set_error("share_filters: lattice sizes or dtype differ");
+            set_error("share_filters: lattice sizes, four-step splits or dtype differ");
             return MR1L_ERR_ARG;
         }
         P->filt_ptr = sh->filt_ptr;

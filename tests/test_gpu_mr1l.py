@@ -291,3 +291,38 @@ def test_large_bluestein_lengths(case, dtype):
     torch.cuda.synchronize()
     assert_close(c.cpu().numpy(), O.forward(p.freqs, p.M, p.z, p.samples, "paper"), dtype, f"forward {name}")
     assert_close(yy.cpu().numpy(), O.adjoint(p.freqs, p.M, p.z, p.coeffs, "paper"), dtype, f"adjoint {name}")
+
+
+SPLIT_CASES = [(13, "c64"), (15, "c128"), (16, "c128"), (18, "c64"), (21, "c64"), (22, "c128")]
+
+
+@pytest.mark.parametrize("lgn,dtype", SPLIT_CASES, ids=[f"lg{a}_{b}" for a, b in SPLIT_CASES])
+def test_every_compiled_split_matches_oracle(lgn, dtype):
+    """Every four-step split compiled for a Bluestein length (the autotuner's candidates) gives the
+    oracle's forward and adjoint; the schedule override is restored afterwards."""
+    torch = require_gpu()
+    import ctypes
+    from paper_1711_05152_amd import _lib
+    from paper_1711_05152_amd.tune_fft import candidates
+    lo, hi = (1 << (lgn - 2)) + 1, 1 << (lgn - 1)
+    p = transform_problem(rng_for(304, lgn), 1500, 6, 40, 2, lo + (hi - lo) // 2, hi, n_rhs=1)
+    ref_c = O.forward(p.freqs, p.M, p.z, p.samples, "paper")
+    ref_y = O.adjoint(p.freqs, p.M, p.z, p.coeffs, "paper")
+    dt = {"c64": _lib.C64, "c128": _lib.C128}[dtype]
+    cur = ctypes.c_int(0)
+    try:
+        for s in candidates(lgn):
+            _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, s, ctypes.byref(cur)), "mr1l_fft_split")
+            assert cur.value == s
+            print(f"split lg{lgn} {dtype} lgN1={s}", flush=True)
+            plan = _plan(p, dtype)
+            c = plan.forward(_to(torch, p.samples, dtype))
+            yy = plan.adjoint(_to(torch, p.coeffs, dtype))
+            torch.cuda.synchronize()
+            assert_close(c.cpu().numpy(), ref_c, dtype, f"forward split {s}")
+            assert_close(yy.cpu().numpy(), ref_y, dtype, f"adjoint split {s}")
+            del plan
+        with pytest.raises(_lib.Mr1lError):
+            _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, 2, None), "mr1l_fft_split")
+    finally:
+        _lib.lib().mr1l_fft_split(dt, lgn, -1, None)
