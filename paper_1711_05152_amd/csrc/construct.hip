@@ -162,6 +162,66 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
     MR1L_HIP_TRY(zdev.alloc((size_t)d * sizeof(int64_t)));
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256));
 
+    if (redraw == 0) {
+        // Alg. 1 itself: lattices L, L+1, ... are tried kSpec at a time with one host
+        // synchronisation.  Each draw depends only on its own stream key (t, call, L) and the
+        // coverage after every lattice is recorded, so keeping the lattices up to the first that
+        // completes the coverage (the later ones are discarded) is exactly the sequential result.
+        constexpr int kSpec = 8;
+        DevMem zk_dev, counts;
+        MR1L_HIP_TRY(zk_dev.alloc((size_t)kSpec * d * sizeof(int64_t)));
+        MR1L_HIP_TRY(counts.alloc((size_t)kSpec * sizeof(unsigned long long)));
+        std::vector<int64_t> zk((size_t)kSpec * d);
+        unsigned long long hc[kSpec];
+        for (int call = 0; call < std::max(1, b); ++call) {
+            out->M.clear();
+            out->z.clear();
+            out->calls = call + 1;
+            MR1L_HIP_TRY(hipMemsetAsync(covered.p, 0, (size_t)n, s));
+            unsigned long long ncov = 0;
+            bool done = false;
+            for (int64_t L = 1; L <= L_max && !done; L += kSpec) {
+                const int nk = (int)std::min<int64_t>(kSpec, L_max - L + 1);
+                for (int i = 0; i < nk; ++i) {
+                    const int64_t M = primes[L + i - 1];
+                    const uint64_t key = Rng::key(seed, {Rng::Z, t, call, L + i});
+                    uint64_t ctr = 0;
+                    for (int c = 0; c < d; ++c) zk[(size_t)i * d + c] = (int64_t)Rng::uniform_int(key, &ctr, (uint64_t)M);
+                }
+                MR1L_HIP_TRY(hipMemcpyAsync(zk_dev.p, zk.data(), (size_t)nk * d * sizeof(int64_t),
+                                            hipMemcpyHostToDevice, s));
+                MR1L_HIP_TRY(hipMemsetAsync(counts.p, 0, (size_t)nk * sizeof(unsigned long long), s));
+                for (int i = 0; i < nk; ++i) {
+                    const int64_t M = primes[L + i - 1];
+                    const int64_t w = (M + 31) / 32;
+                    const int64_t* zi = zk_dev.as<int64_t>() + (size_t)i * d;
+                    MR1L_HIP_TRY(hipMemsetAsync(bm.p, 0, 2 * w * sizeof(uint32_t), s));
+                    hipLaunchKernelGGL(k_trial_hist<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n, zi, M,
+                                       1.0 / (double)M, fast, bm.as<uint32_t>(), w);
+                    hipLaunchKernelGGL(k_trial_cover<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n, zi,
+                                       M, 1.0 / (double)M, fast, (const uint32_t*)bm.p, w, covered.as<uint8_t>(),
+                                       counts.as<unsigned long long>() + i);
+                }
+                MR1L_HIP_TRY(hipGetLastError());
+                MR1L_HIP_TRY(hipMemcpyAsync(hc, counts.p, (size_t)nk * sizeof(unsigned long long),
+                                            hipMemcpyDeviceToHost, s));
+                MR1L_HIP_TRY(hipStreamSynchronize(s));
+                for (int i = 0; i < nk; ++i) {
+                    out->M.push_back(primes[L + i - 1]);
+                    out->z.insert(out->z.end(), zk.begin() + (size_t)i * d, zk.begin() + (size_t)(i + 1) * d);
+                    ncov = hc[i];
+                    if ((int64_t)ncov == n) {
+                        done = true;
+                        break;
+                    }
+                }
+            }
+            out->uncovered = n - (int64_t)ncov;
+            if (out->uncovered == 0) break;
+        }
+        return MR1L_OK;
+    }
+
     std::vector<int64_t> zl(d);
     for (int call = 0; call < std::max(1, b); ++call) {
         out->M.clear();
