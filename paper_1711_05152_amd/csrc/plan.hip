@@ -76,6 +76,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     P->n = n;
     P->L = L;
     MR1L_HIP_TRY(hipSetDevice(sp.device));
+    TableStager stg(TableStager::PLAN);   // host tables -> device, flushed before the first kernel
 
     // ---- frequencies ----
     int64_t maxabs = 0;
@@ -95,7 +96,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         if (ktype == K_I8) pack_soa<int8_t>(sp.host_freqs, n, d, packed);
         else if (ktype == K_I16) pack_soa<int16_t>(sp.host_freqs, n, d, packed);
         else pack_soa<int32_t>(sp.host_freqs, n, d, packed);
-        MR1L_HIP_TRY(P->freqs.upload(packed.data(), packed.size()));
+        MR1L_HIP_TRY(stg.add(P->freqs, packed.data(), packed.size()));
         P->args.fv.f = P->freqs.p;
     } else {
         ktype = sp.dev_ktype;
@@ -139,7 +140,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         std::vector<int32_t> z32((size_t)std::max(1, L) * zrow, 0);
         for (int l = 0; l < L; ++l)
             for (int c = 0; c < d; ++c) z32[(size_t)l * zrow + c] = (int32_t)zred[(size_t)l * d + c];
-        MR1L_HIP_TRY(P->z32.upload(z32.data(), z32.size() * sizeof(int32_t)));
+        MR1L_HIP_TRY(stg.add(P->z32, z32.data(), z32.size() * sizeof(int32_t)));
         P->args.zpad = zp;
         P->args.zrow = zrow;
         P->args.z32 = P->z32.as<int32_t>();
@@ -188,10 +189,9 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
 
     for (int i = 0; i < ntx; ++i)
         for (int l = P->htx[i].lat0; l < P->htx[i].lat0 + P->htx[i].nlat; ++l) P->hdesc[l].tx = i;
-    MR1L_HIP_TRY(P->desc.upload(P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
-    MR1L_HIP_TRY(P->tx.upload(P->htx.data(), P->htx.size() * sizeof(TxDesc)));
-    MR1L_HIP_TRY(P->tx_foff.upload(foff.data(), foff.size() * sizeof(int64_t)));
-    MR1L_HIP_TRY(P->z.upload(zred.data(), zred.size() * sizeof(int64_t)));
+    MR1L_HIP_TRY(stg.add(P->tx, P->htx.data(), P->htx.size() * sizeof(TxDesc)));
+    MR1L_HIP_TRY(stg.add(P->tx_foff, foff.data(), foff.size() * sizeof(int64_t)));
+    MR1L_HIP_TRY(stg.add(P->z, zred.data(), zred.size() * sizeof(int64_t)));
     {
         std::vector<int> ids;
         std::vector<std::pair<int, int>> spans;   // (lgN, first index)
@@ -199,7 +199,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             spans.push_back({kv.first, (int)ids.size()});
             ids.insert(ids.end(), kv.second.begin(), kv.second.end());
         }
-        MR1L_HIP_TRY(P->grp_lat.upload(ids.data(), ids.size() * sizeof(int)));
+        MR1L_HIP_TRY(stg.add(P->grp_lat, ids.data(), ids.size() * sizeof(int)));
         for (size_t i = 0; i < spans.size(); ++i) {
             FftGroup g;
             g.lgN = spans[i].first;
@@ -236,7 +236,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         for (size_t i = 0; i < most; ++i)
             for (auto& v : byx) tiles.push_back(i < v.size() ? v[i] : HistTile{-1, 0, 0, 0});
     }
-    MR1L_HIP_TRY(P->hist.upload(tiles.data(), tiles.size() * sizeof(HistTile)));
+    MR1L_HIP_TRY(stg.add(P->hist, tiles.data(), tiles.size() * sizeof(HistTile)));
     // fused residue + histogram tiles: each lattice's frequencies split into chunks of one
     // workgroup iteration, each counted over all bins of the lattice in LDS
     bool fused = L > 0 && n < ((int64_t)1 << 31);   // 32-bit frequency offsets inside the kernel
@@ -264,8 +264,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             }
             D.rtn = (int32_t)rtiles.size() - D.rt0;
         }
-        MR1L_HIP_TRY(P->desc.upload(P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
-        MR1L_HIP_TRY(P->rtiles.upload(rtiles.data(), rtiles.size() * sizeof(ResTile)));
+        MR1L_HIP_TRY(stg.add(P->rtiles, rtiles.data(), rtiles.size() * sizeof(ResTile)));
         MR1L_HIP_TRY(P->part.alloc((size_t)std::max<int64_t>(1, part_words) * sizeof(uint32_t)));
     }
     const int64_t rstride = (n + 3) / 4 * 4;
@@ -297,7 +296,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     if (P->args.bsort) {
         const int64_t nchunks = (P->sum_M + kScanChunk - 1) / kScanChunk;
         MR1L_HIP_TRY(P->bcnt.alloc((size_t)P->sum_M * sizeof(int32_t)));
-        MR1L_HIP_TRY(hipMemset(P->bcnt.p, 0, (size_t)P->sum_M * sizeof(int32_t)));
+        MR1L_HIP_TRY(hipMemsetAsync(P->bcnt.p, 0, (size_t)P->sum_M * sizeof(int32_t), nullptr));
         MR1L_HIP_TRY(P->bloc.alloc((size_t)P->sum_M * sizeof(int32_t)));
         MR1L_HIP_TRY(P->bbase.alloc((size_t)std::max<int64_t>(1, nchunks) * sizeof(int32_t)));
         MR1L_HIP_TRY(P->perm.alloc((size_t)std::max<int64_t>(4, (int64_t)max_nlat * rstride) * sizeof(int32_t)));
@@ -334,6 +333,10 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     a.rt_words = rt_words;
     a.part = P->part.as<uint32_t>();
 
+    // lattice descriptors as complete (fused-pass tiles included), then every staged table
+    MR1L_HIP_TRY(stg.add(P->desc, P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
+    a.desc = P->desc.as<LatDesc>();
+    MR1L_HIP_TRY(stg.flush(nullptr));
     if (!twiddles<T>(sp.device) || !twiddles<double>(sp.device)) {
         set_error("could not allocate twiddle tables");
         return MR1L_ERR_NOMEM;

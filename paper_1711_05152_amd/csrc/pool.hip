@@ -17,6 +17,8 @@
 //   * a hipMalloc that fails for lack of memory empties the device's cache and is retried once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -149,6 +151,49 @@ void pool_free(void* p, size_t c, int dev) {
         }
     }
     (void)hipFree(p);
+}
+
+hipError_t TableStager::add(DevMem& dst, const void* src, size_t bytes) {
+    hipError_t e = dst.alloc(bytes);
+    if (e != hipSuccess || bytes == 0) return e;
+    const size_t off = (host.size() + 255) & ~(size_t)255;
+    host.resize(off + bytes);
+    std::memcpy(host.data() + off, src, bytes);
+    items.push_back(Item{&dst, off, bytes});
+    return hipSuccess;
+}
+
+hipError_t TableStager::flush(hipStream_t st) {
+    thread_local void* pinned[2] = {nullptr, nullptr};
+    thread_local size_t cap[2] = {0, 0};
+    thread_local hipEvent_t done[2] = {nullptr, nullptr};   // copies of the slot's last flush
+    if (items.empty()) return hipSuccess;
+    if (done[slot]) {
+        hipError_t e = hipEventSynchronize(done[slot]);
+        if (e != hipSuccess) return e;
+    } else {
+        hipError_t e = hipEventCreateWithFlags(&done[slot], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    if (cap[slot] < host.size()) {
+        if (pinned[slot]) (void)hipHostFree(pinned[slot]);
+        pinned[slot] = nullptr;
+        cap[slot] = 0;
+        const size_t want = std::max<size_t>(host.size(), (size_t)1 << 20);
+        hipError_t e = hipHostMalloc(&pinned[slot], want, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        cap[slot] = want;
+    }
+    std::memcpy(pinned[slot], host.data(), host.size());
+    for (const Item& it : items) {
+        hipError_t e = hipMemcpyAsync(it.dst->p, (char*)pinned[slot] + it.off, it.bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(done[slot], st);
+    if (e != hipSuccess) return e;
+    items.clear();
+    host.clear();
+    return hipSuccess;
 }
 
 }  // namespace mr1l

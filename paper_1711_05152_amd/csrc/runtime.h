@@ -77,6 +77,24 @@ struct DevMem {
     template <typename U> U* as() const { return (U*)p; }
 };
 
+// Small host tables (descriptors, generating vectors, tile lists) on their way to the device: each
+// add() allocates the device buffer and appends the bytes to a host list; flush() copies the list
+// into a pinned buffer owned by the calling thread (one per slot) and queues one asynchronous copy
+// per table on the stream, ordered before the kernels that read them.  A flush first waits for the
+// copies of the slot's previous flush (an event), so the pinned bytes outlive their copies.  The
+// device buffers must not be released before the copies have run (the stream is synchronised
+// before they go out of scope).
+struct TableStager {
+    enum Slot { PLAN = 0, DRIVER = 1 };
+    explicit TableStager(Slot s) : slot(s) {}
+    hipError_t add(DevMem& dst, const void* src, size_t bytes);
+    hipError_t flush(hipStream_t st);
+    Slot slot;
+    struct Item { DevMem* dst; size_t off, bytes; };
+    std::vector<Item> items;
+    std::vector<char> host;
+};
+
 // Counter-based SplitMix64 streams (published generator; the key derivation is this project's):
 //   key(seed, f1..fm): k = seed; k = mix64(k + GAMMA (f + 1)) for each field f
 //   draw(k, c) = mix64(k + GAMMA (c + 1))

@@ -128,9 +128,13 @@ mr1l_status detect_1d(Ctx& C, std::vector<DevMem>& It, std::vector<int64_t>& nIt
             }
         t0 = clk::now();
         DevMem dA, dComp, dKeys, y, w, coeffs, flags, idx, cnt;
-        MR1L_HIP_TRY(dA.upload(anchors.data(), anchors.size() * sizeof(double)));
-        MR1L_HIP_TRY(dComp.upload(comp.data(), comp.size() * sizeof(int)));
-        MR1L_HIP_TRY(dKeys.upload(keys.data(), keys.size() * sizeof(uint64_t)));
+        {
+            TableStager stg(TableStager::DRIVER);
+            MR1L_HIP_TRY(stg.add(dA, anchors.data(), anchors.size() * sizeof(double)));
+            MR1L_HIP_TRY(stg.add(dComp, comp.data(), comp.size() * sizeof(int)));
+            MR1L_HIP_TRY(stg.add(dKeys, keys.data(), keys.size() * sizeof(uint64_t)));
+            MR1L_HIP_TRY(stg.flush(C.st));
+        }
         MR1L_HIP_TRY(y.alloc((size_t)njobs * K * csz));
         if (C.planted) {
             MR1L_HIP_TRY(w.alloc((size_t)njobs * std::max<int64_t>(1, C.s_pl) * 16));
@@ -290,8 +294,12 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
         }
         t0 = clk::now();
         DevMem dA, dKeys, y;
-        MR1L_HIP_TRY(dA.upload(anchors.data(), anchors.size() * sizeof(double)));
-        MR1L_HIP_TRY(dKeys.upload(keys.data(), keys.size() * sizeof(uint64_t)));
+        {
+            TableStager stg(TableStager::DRIVER);
+            MR1L_HIP_TRY(stg.add(dA, anchors.data(), anchors.size() * sizeof(double)));
+            MR1L_HIP_TRY(stg.add(dKeys, keys.data(), keys.size() * sizeof(uint64_t)));
+            MR1L_HIP_TRY(stg.flush(C.st));
+        }
         MR1L_HIP_TRY(y.alloc((size_t)rt * std::max<int64_t>(1, sumM) * csz));
         if (C.planted) {
             if (C.s_pl > 0) {
@@ -328,9 +336,13 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
             std::vector<int64_t> off(L + 1, 0);
             for (int l = 0; l < L; ++l) off[l + 1] = off[l] + cr.M[l];
             MR1L_HIP_TRY(nodes.alloc((size_t)sumM * d * sizeof(double)));
-            MR1L_HIP_TRY(dM.upload(cr.M.data(), L * sizeof(int64_t)));
-            MR1L_HIP_TRY(dOff.upload(off.data(), off.size() * sizeof(int64_t)));
-            MR1L_HIP_TRY(dZ.upload(cr.z.data(), cr.z.size() * sizeof(int64_t)));
+            {
+                TableStager stg(TableStager::DRIVER);
+                MR1L_HIP_TRY(stg.add(dM, cr.M.data(), L * sizeof(int64_t)));
+                MR1L_HIP_TRY(stg.add(dOff, off.data(), off.size() * sizeof(int64_t)));
+                MR1L_HIP_TRY(stg.add(dZ, cr.z.data(), cr.z.size() * sizeof(int64_t)));
+                MR1L_HIP_TRY(stg.flush(C.st));
+            }
             const int64_t maxM = *std::max_element(cr.M.begin(), cr.M.end());
             for (int i = 0; i < rt; ++i) {
                 sf_nodes_lattice(dM.as<int64_t>(), dOff.as<int64_t>(), dZ.as<int64_t>(), L, maxM, t, d,
