@@ -158,17 +158,30 @@ __device__ __forceinline__ unsigned int block_sum_u32(unsigned int v, unsigned i
     return r;
 }
 
-// inclusive scan of v over the block
+// inclusive scan over the workgroup: within each wavefront by shuffles, then over the 16 wave
+// totals by the first wavefront (sh: at least kSelThreads / 64 entries; free again on return)
 __device__ __forceinline__ unsigned int block_scan_u32(unsigned int v, unsigned int* sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kSelThreads; off <<= 1) {
-        const unsigned int add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
+    constexpr int kWaves = kSelThreads / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    const unsigned int r = sh[threadIdx.x];
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    if (wv == 0) {
+        unsigned int t = lane < kWaves ? sh[lane] : 0u;
+#pragma unroll
+        for (int off = 1; off < kWaves; off <<= 1) {
+            const unsigned int y = __shfl_up(t, off);
+            if (lane >= off) t += y;
+        }
+        if (lane < kWaves) sh[lane] = t;
+    }
+    __syncthreads();
+    const unsigned int r = x + (wv > 0 ? sh[wv - 1] : 0u);
     __syncthreads();
     return r;
 }
@@ -239,16 +252,25 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const cx<T>* __restrict_
     }
 }
 
-// indices of nonzero flags, ascending; *count = their number (one workgroup)
+// indices of nonzero flags, ascending; *count = their number (one workgroup; each thread takes 16
+// consecutive flags per pass, so a pass covers 16384 flags with one block scan)
+constexpr int kCompactPer = 16;
 __global__ __launch_bounds__(kSelThreads) void k_compact(const uint8_t* __restrict__ flags, int64_t n, int32_t* idx,
                                                          int64_t* count) {
     __shared__ unsigned int sh[kSelThreads];
     int64_t base = 0;
-    for (int64_t k0 = 0; k0 < n; k0 += kSelThreads) {
-        const int64_t k = k0 + threadIdx.x;
-        const unsigned int f = (k < n && flags[k]) ? 1u : 0u;
-        const unsigned int incl = block_scan_u32(f, sh);
-        if (f) idx[base + incl - 1] = (int32_t)k;
+    for (int64_t k0 = 0; k0 < n; k0 += (int64_t)kSelThreads * kCompactPer) {
+        const int64_t kb = k0 + (int64_t)threadIdx.x * kCompactPer;
+        unsigned int bits = 0;
+#pragma unroll
+        for (int i = 0; i < kCompactPer; ++i)
+            if (kb + i < n && flags[kb + i]) bits |= 1u << i;
+        const unsigned int c = __popc(bits);
+        const unsigned int incl = block_scan_u32(c, sh);
+        int64_t pos = base + incl - c;
+#pragma unroll
+        for (int i = 0; i < kCompactPer; ++i)
+            if ((bits >> i) & 1u) idx[pos++] = (int32_t)(kb + i);
         if (threadIdx.x == kSelThreads - 1) sh[0] = incl;
         __syncthreads();
         base += sh[0];
