@@ -3,9 +3,12 @@
 //
 // Host side: L_max and lambda (Alg. 1 first two steps), the prime sizes p > lambda of P^I found by
 // trial division with a cached table of small primes, and the random generating vectors
-// (SplitMix64 Z stream keyed by (t, call, L)).  Device side: for every trial lattice the residues
-// of all frequencies, the alias bitmaps and the running union of the unaliased sets, followed by
-// one device-to-host copy of the number of covered frequencies (the stopping test of Alg. 1).
+// (SplitMix64 Z stream keyed by (t, call, L)).  Device side, for rounds of up to eight trial
+// lattices: the residues of all frequencies and the alias bitmaps of every lattice of the round
+// (one launch), then one pass that extends the running union of the unaliased sets and counts the
+// covered frequencies after each lattice of the round, and one device-to-host copy of those counts
+// (the stopping test of Alg. 1, applied lattice by lattice on the host).  The construction variant
+// with redraws keeps one lattice per round.
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -56,6 +59,71 @@ __global__ __launch_bounds__(256) void k_trial_cover(const K* __restrict__ f, in
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicAdd(count, (unsigned long long)part[0]);
+}
+
+// Batched trials (Alg. 1 itself): lattices i = 0..nk-1 of a round, generating vectors z[i][d],
+// sizes M[i]; bitmaps of lattice i at bm + i * 2 * wstride (seen, then multi at + wstride).
+constexpr int kSpec = 8;
+struct TrialRound {
+    int64_t M[kSpec];
+    double invM[kSpec];
+    int nk;
+};
+
+// grid (blocks, nk): alias bitmaps of every lattice of the round
+template <typename K>
+__global__ __launch_bounds__(256) void k_trial_hist_round(const K* __restrict__ f, int64_t nf, int d, int64_t n,
+                                                          const int64_t* __restrict__ z, TrialRound tr, int fast,
+                                                          uint32_t* bm, int64_t wstride) {
+    const int i = blockIdx.y;
+    const int64_t M = tr.M[i];
+    uint32_t* b = bm + (int64_t)i * 2 * wstride;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = dot_kz<K>(f, nf, d, g, z + (int64_t)i * d);
+        const int64_t r = fast ? mod_fast(s, M, tr.invM[i]) : mod_exact(s, M);
+        const uint32_t bit = 1u << (r & 31);
+        const uint32_t old = atomicOr(b + (r >> 5), bit);
+        if (old & bit) atomicOr(b + wstride + (r >> 5), bit);
+    }
+}
+
+// one pass over the frequencies: counts[i] = number covered once lattices 0..i of the round are
+// added to the running union; covered becomes the union with all nk lattices
+template <typename K>
+__global__ __launch_bounds__(256) void k_trial_cover_round(const K* __restrict__ f, int64_t nf, int d, int64_t n,
+                                                           const int64_t* __restrict__ z, TrialRound tr, int fast,
+                                                           const uint32_t* __restrict__ bm, int64_t wstride,
+                                                           uint8_t* covered, unsigned long long* counts) {
+    __shared__ unsigned int part[kSpec][256];
+    unsigned int local[kSpec];
+#pragma unroll
+    for (int i = 0; i < kSpec; ++i) local[i] = 0;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        int first = covered[g] ? 0 : kSpec;   // first lattice of the round after which g is covered
+        if (first) {
+            for (int i = 0; i < tr.nk; ++i) {
+                const int64_t s = dot_kz<K>(f, nf, d, g, z + (int64_t)i * d);
+                const int64_t r = fast ? mod_fast(s, tr.M[i], tr.invM[i]) : mod_exact(s, tr.M[i]);
+                if (!((bm[(int64_t)i * 2 * wstride + wstride + (r >> 5)] >> (r & 31)) & 1u)) {
+                    first = i;
+                    break;
+                }
+            }
+            if (first < tr.nk) covered[g] = 1;
+        }
+#pragma unroll
+        for (int i = 0; i < kSpec; ++i) local[i] += first <= i;
+    }
+#pragma unroll
+    for (int i = 0; i < kSpec; ++i) part[i][threadIdx.x] = local[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int i = 0; i < kSpec; ++i) part[i][threadIdx.x] += part[i][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < kSpec && (int)threadIdx.x < tr.nk) atomicAdd(counts + threadIdx.x, (unsigned long long)part[threadIdx.x][0]);
 }
 
 // any pair a < b with k_a = k_b componentwise mod p  ->  *found = 1
@@ -167,10 +235,10 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
         // synchronisation.  Each draw depends only on its own stream key (t, call, L) and the
         // coverage after every lattice is recorded, so keeping the lattices up to the first that
         // completes the coverage (the later ones are discarded) is exactly the sequential result.
-        constexpr int kSpec = 8;
-        DevMem zk_dev, counts;
+        DevMem zk_dev, counts, bmr;
         MR1L_HIP_TRY(zk_dev.alloc((size_t)kSpec * d * sizeof(int64_t)));
         MR1L_HIP_TRY(counts.alloc((size_t)kSpec * sizeof(unsigned long long)));
+        MR1L_HIP_TRY(bmr.alloc((size_t)kSpec * 2 * words * sizeof(uint32_t)));
         std::vector<int64_t> zk((size_t)kSpec * d);
         unsigned long long hc[kSpec];
         for (int call = 0; call < std::max(1, b); ++call) {
@@ -181,32 +249,30 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
             unsigned long long ncov = 0;
             bool done = false;
             for (int64_t L = 1; L <= L_max && !done; L += kSpec) {
-                const int nk = (int)std::min<int64_t>(kSpec, L_max - L + 1);
-                for (int i = 0; i < nk; ++i) {
+                TrialRound tr{};
+                tr.nk = (int)std::min<int64_t>(kSpec, L_max - L + 1);
+                for (int i = 0; i < tr.nk; ++i) {
                     const int64_t M = primes[L + i - 1];
+                    tr.M[i] = M;
+                    tr.invM[i] = 1.0 / (double)M;
                     const uint64_t key = Rng::key(seed, {Rng::Z, t, call, L + i});
                     uint64_t ctr = 0;
                     for (int c = 0; c < d; ++c) zk[(size_t)i * d + c] = (int64_t)Rng::uniform_int(key, &ctr, (uint64_t)M);
                 }
-                MR1L_HIP_TRY(hipMemcpyAsync(zk_dev.p, zk.data(), (size_t)nk * d * sizeof(int64_t),
+                MR1L_HIP_TRY(hipMemcpyAsync(zk_dev.p, zk.data(), (size_t)tr.nk * d * sizeof(int64_t),
                                             hipMemcpyHostToDevice, s));
-                MR1L_HIP_TRY(hipMemsetAsync(counts.p, 0, (size_t)nk * sizeof(unsigned long long), s));
-                for (int i = 0; i < nk; ++i) {
-                    const int64_t M = primes[L + i - 1];
-                    const int64_t w = (M + 31) / 32;
-                    const int64_t* zi = zk_dev.as<int64_t>() + (size_t)i * d;
-                    MR1L_HIP_TRY(hipMemsetAsync(bm.p, 0, 2 * w * sizeof(uint32_t), s));
-                    hipLaunchKernelGGL(k_trial_hist<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n, zi, M,
-                                       1.0 / (double)M, fast, bm.as<uint32_t>(), w);
-                    hipLaunchKernelGGL(k_trial_cover<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n, zi,
-                                       M, 1.0 / (double)M, fast, (const uint32_t*)bm.p, w, covered.as<uint8_t>(),
-                                       counts.as<unsigned long long>() + i);
-                }
+                MR1L_HIP_TRY(hipMemsetAsync(counts.p, 0, (size_t)tr.nk * sizeof(unsigned long long), s));
+                MR1L_HIP_TRY(hipMemsetAsync(bmr.p, 0, (size_t)tr.nk * 2 * words * sizeof(uint32_t), s));
+                hipLaunchKernelGGL(k_trial_hist_round<K>, dim3(blocks, tr.nk), dim3(256), 0, s, (const K*)f, n, d, n,
+                                   zk_dev.as<int64_t>(), tr, fast, bmr.as<uint32_t>(), words);
+                hipLaunchKernelGGL(k_trial_cover_round<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
+                                   zk_dev.as<int64_t>(), tr, fast, (const uint32_t*)bmr.p, words,
+                                   covered.as<uint8_t>(), counts.as<unsigned long long>());
                 MR1L_HIP_TRY(hipGetLastError());
-                MR1L_HIP_TRY(hipMemcpyAsync(hc, counts.p, (size_t)nk * sizeof(unsigned long long),
+                MR1L_HIP_TRY(hipMemcpyAsync(hc, counts.p, (size_t)tr.nk * sizeof(unsigned long long),
                                             hipMemcpyDeviceToHost, s));
                 MR1L_HIP_TRY(hipStreamSynchronize(s));
-                for (int i = 0; i < nk; ++i) {
+                for (int i = 0; i < tr.nk; ++i) {
                     out->M.push_back(primes[L + i - 1]);
                     out->z.insert(out->z.end(), zk.begin() + (size_t)i * d, zk.begin() + (size_t)(i + 1) * d);
                     ncov = hc[i];
