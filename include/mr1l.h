@@ -163,7 +163,9 @@ mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current);
  *   max_idle_bytes  new cap (0 disables caching); < 0 keeps the current cap
  *   released        optional out: bytes returned to the driver by this call
  * Returns every idle block of the device to the driver (after a device-wide synchronisation) and
- * then applies the cap.  Errors: MR1L_ERR_ARG for an invalid device. */
+ * then applies the cap.  The library also keeps the Bluestein filter spectra of recent plans per
+ * device (at most 1 GiB, spectra up to 64 MiB; a plan whose lattice sizes all hit copies them
+ * instead of recomputing); this call drops them too.  Errors: MR1L_ERR_ARG for an invalid device. */
 mr1l_status mr1l_memory_cache(int device, int64_t max_idle_bytes, int64_t* released);
 
 /* Release a plan and its device memory (NULL is accepted). */

@@ -4,6 +4,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <numeric>
 #include <string>
 
@@ -54,6 +56,108 @@ static void pack_soa(const int32_t* f, int64_t n, int d, std::vector<char>& out)
     K* o = (K*)out.data();
     for (int64_t g = 0; g < n; ++g)
         for (int c = 0; c < d; ++c) o[(size_t)c * n + g] = (K)f[g * d + c];
+}
+
+// Filter spectra of earlier plans, per device: the spectrum of a lattice depends only on (M, the
+// Bluestein length, the four-step split, the precision), and the steps of Alg. 3 and repeated
+// solves meet the same prime sizes again.  Spectra up to 64 MiB are kept, at most 1 GiB per
+// device, least recently used out first; mr1l_memory_cache empties the device's entries.
+namespace {
+struct FiltKey {
+    int dev, dtype, lgN, lgN1;
+    int64_t M;
+    bool operator<(const FiltKey& o) const {
+        return std::tie(dev, dtype, lgN, lgN1, M) < std::tie(o.dev, o.dtype, o.lgN, o.lgN1, o.M);
+    }
+};
+struct FiltEntry {
+    DevMem buf;
+    uint64_t used = 0;
+};
+constexpr size_t kFiltEntryMax = (size_t)64 << 20;
+constexpr size_t kFiltCacheMax = (size_t)1 << 30;
+// never destroyed: entries hand their blocks back to the allocator, which must outlive them
+std::mutex& fc_mutex() {
+    static std::mutex* m = new std::mutex;
+    return *m;
+}
+std::map<FiltKey, FiltEntry>& fc_map() {
+    static auto* m = new std::map<FiltKey, FiltEntry>;
+    return *m;
+}
+size_t g_fc_bytes = 0;
+uint64_t g_fc_clock = 0;
+}  // namespace
+
+void filter_cache_clear(int dev) {
+    std::lock_guard<std::mutex> lk(fc_mutex());
+    auto& m = fc_map();
+    for (auto it = m.begin(); it != m.end();) {
+        if (it->first.dev == dev) {
+            g_fc_bytes -= it->second.buf.bytes;
+            it = m.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// copy every lattice's spectrum from the cache, or (any missing) build them all and remember the
+// missing ones; on the null stream, like the rest of plan creation
+template <typename T>
+static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
+    const int L = P->L;
+    cx<T>* filt = (cx<T>*)P->filt_ptr;
+    std::vector<int> miss;
+    {
+        std::lock_guard<std::mutex> lk(fc_mutex());
+        auto& m = fc_map();
+        std::vector<std::pair<const FiltEntry*, int>> hits;
+        for (int l = 0; l < L; ++l) {
+            const LatDesc& D = P->hdesc[l];
+            auto it = m.find(FiltKey{device, (int)P->dtype, D.lgN, D.lgN1, D.M});
+            if (it == m.end()) miss.push_back(l);
+            else hits.push_back({&it->second, l});
+        }
+        if (miss.empty()) {
+            for (auto& h : hits) {
+                const LatDesc& D = P->hdesc[h.second];
+                hipError_t e = hipMemcpyAsync(filt + D.filt_off, h.first->buf.p, ((size_t)1 << D.lgN) * sizeof(cx<T>),
+                                              hipMemcpyDeviceToDevice, nullptr);
+                if (e != hipSuccess) return e;
+                const_cast<FiltEntry*>(h.first)->used = ++g_fc_clock;
+            }
+            return hipSuccess;
+        }
+    }
+    hipError_t e = build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, filt, device, nullptr);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(fc_mutex());
+    auto& m = fc_map();
+    for (int l : miss) {
+        const LatDesc& D = P->hdesc[l];
+        const size_t bytes = ((size_t)1 << D.lgN) * sizeof(cx<T>);
+        const FiltKey key{device, (int)P->dtype, D.lgN, D.lgN1, D.M};
+        if (bytes > kFiltEntryMax || m.count(key)) continue;
+        FiltEntry ent;
+        if (ent.buf.alloc(bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            break;   // no room: the cache is an optimisation only
+        }
+        e = hipMemcpyAsync(ent.buf.p, filt + D.filt_off, bytes, hipMemcpyDeviceToDevice, nullptr);
+        if (e != hipSuccess) return e;
+        ent.used = ++g_fc_clock;
+        g_fc_bytes += bytes;
+        m.emplace(key, std::move(ent));
+        while (g_fc_bytes > kFiltCacheMax) {
+            auto old = m.begin();
+            for (auto it = m.begin(); it != m.end(); ++it)
+                if (it->second.used < old->second.used) old = it;
+            g_fc_bytes -= old->second.buf.bytes;
+            m.erase(old);
+        }
+    }
+    return hipSuccess;
 }
 
 template <typename T>
@@ -341,7 +445,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         set_error("could not allocate twiddle tables");
         return MR1L_ERR_NOMEM;
     }
-    if (!sh) MR1L_HIP_TRY(build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, (cx<T>*)P->filt_ptr, sp.device, nullptr));
+    if (!sh) MR1L_HIP_TRY(plan_filters<T>(P, a, sp.device));
     MR1L_HIP_TRY(hipGetLastError());
     MR1L_HIP_TRY(hipDeviceSynchronize());
     *out = guard.release();

@@ -207,6 +207,7 @@ extern "C" mr1l_status mr1l_memory_cache(int device, int64_t max_idle_bytes, int
         set_error("invalid device for mr1l_memory_cache");
         return MR1L_ERR_ARG;
     }
+    filter_cache_clear(device);   // its blocks return to the cache's idle lists first
     std::lock_guard<std::mutex> lk(g_mu);
     const size_t freed = trim_locked(device);
     if (max_idle_bytes >= 0) cache_of(device).limit = max_idle_bytes;

@@ -24,6 +24,9 @@ void clear_error();
         }                                                                                            \
     } while (0)
 
+// Spectra kept across plans (plan.hip); mr1l_memory_cache drops a device's entries.
+void filter_cache_clear(int dev);
+
 // Caching device allocator (pool.hip): every DevMem goes through it.
 hipError_t pool_alloc(void** p, size_t bytes, int* dev, size_t* block);
 void pool_free(void* p, size_t block, int dev);

@@ -240,8 +240,8 @@ def test_eval_adjoint_crowded_bins():
 
 def test_memory_cache_reuse_and_release():
     """Plans created one after another reuse the library's cached device blocks (stale contents
-    included) and give the same results; the cache gives its idle blocks back on request and can be
-    switched off."""
+    included) and cached filter spectra, and give the same results; the cache gives its idle blocks
+    back on request and can be switched off."""
     torch = require_gpu()
     from paper_1711_05152_amd.mr1l import memory_cache
     name, n, d, box, L, mlo, mhi, n_rhs = CASES[3]
@@ -258,6 +258,8 @@ def test_memory_cache_reuse_and_release():
     assert memory_cache(0) == 0
     for o in outs:
         assert_close(o, c_ref, "c128", "forward after reuse")
+    # the later plans copy the first one's filter spectra from the library's spectrum cache
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     default_cap = torch.cuda.get_device_properties(0).total_memory // 4
     try:
         memory_cache(0, 0)
