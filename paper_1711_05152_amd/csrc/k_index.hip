@@ -351,6 +351,18 @@ __global__ __launch_bounds__(256) void k_gather(TxArgs a, const cx<T>* __restric
 constexpr int kSplit = 8;
 constexpr int kSplitSlots = 2;   // slots per lane per pass (16 lattice slots of a frequency)
 
+// transform of frequency g for a group of kSplit lanes: lane 0 of the group searches, the others
+// take its answer (the binary search over the transform offsets is the slow part for many
+// transforms)
+template <bool SINGLE>
+__device__ __forceinline__ TxDesc split_tx(const TxArgs& a, int64_t g, int sub, int lead) {
+    if (SINGLE) return TxDesc{0, a.n, 0, a.L};
+    int ti = 0;
+    if (sub == 0) ti = find_tx(a.tx_foff, a.ntx + 1, g);
+    ti = __shfl(ti, lead);
+    return a.tx[ti];
+}
+
 // loads of the residues and alias words of slots j0 + u kSplit + sub (clamped to the last slot)
 __device__ __forceinline__ void split_slots(const TxArgs& a, const TxDesc& t, int j0, int sub, int64_t g,
                                             int32_t* r, uint32_t* w) {
@@ -370,7 +382,7 @@ __global__ __launch_bounds__(256) void k_gather_split(TxArgs a, const cx<T>* __r
     const int lead = (int)(threadIdx.x & 63) & ~(kSplit - 1);      // lane of sub 0 in the wave
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / kSplit;
     for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSplit; g < a.n; g += stride) {
-        const TxDesc t = get_tx<SINGLE>(a, g);
+        const TxDesc t = split_tx<SINGLE>(a, g, sub, lead);
         cx<T> acc = {(T)0, (T)0};
         int cnt = 0;
         for (int j0 = 0; j0 < t.nlat; j0 += kSplit * kSplitSlots) {
@@ -407,9 +419,10 @@ template <typename T, bool SINGLE>
 __global__ __launch_bounds__(256) void k_scatter_split(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
     constexpr int SPAN = kSplit * kSplitSlots;
     const int sub = threadIdx.x & (kSplit - 1);
+    const int lead = (int)(threadIdx.x & 63) & ~(kSplit - 1);      // lane of sub 0 in the wave
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / kSplit;
     for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSplit; g < a.n; g += stride) {
-        const TxDesc t = get_tx<SINGLE>(a, g);
+        const TxDesc t = split_tx<SINGLE>(a, g, sub, lead);
         if (t.nlat == 0) continue;
         const cx<T> c = coeffs[g];
         // counter_k over all slots (the first pass's slots are kept for the writes)
@@ -735,6 +748,11 @@ void launch_alias(const TxArgs& a, bool histogram, hipStream_t s) {
         hipLaunchKernelGGL(k_hist_lds, dim3(a.nhist), dim3(kHistThreads), 2 * a.hist_words * sizeof(uint32_t), s, a);
 }
 
+// The lane-split gather/scatter read each residue row in 32-byte pieces (a wavefront covers 8
+// frequencies); that pays while the residue rows stay in cache and costs HBM traffic beyond
+// (measured: 18.6 million frequencies of 512 transforms, 5.6 / 7.4 ms split against ~4 ms).
+static inline bool split_pays(const TxArgs& a) { return a.n * (int64_t)a.max_nlat * 4 <= ((int64_t)64 << 20); }
+
 template <typename T>
 void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval, hipStream_t s) {
     if (a.n == 0 || a.n_rhs == 0) return;
@@ -744,7 +762,7 @@ void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval,
         const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
         if (eval && single) hipLaunchKernelGGL((k_gather<T, true, true, RB>), grid, dim3(256), 0, s, a, work, coeffs);
         else if (eval) hipLaunchKernelGGL((k_gather<T, true, false, RB>), grid, dim3(256), 0, s, a, work, coeffs);
-        else if (RB == 1) {
+        else if (RB == 1 && split_pays(a)) {
             const dim3 g4(grid_for(a.n * kSplit));
             if (single) hipLaunchKernelGGL((k_gather_split<T, true>), g4, dim3(256), 0, s, a, work, coeffs);
             else hipLaunchKernelGGL((k_gather_split<T, false>), g4, dim3(256), 0, s, a, work, coeffs);
@@ -771,7 +789,7 @@ void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval
         const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
         if (eval && single) hipLaunchKernelGGL((k_scatter_eval<T, true, RB>), grid, dim3(256), 0, s, a, coeffs, work);
         else if (eval) hipLaunchKernelGGL((k_scatter_eval<T, false, RB>), grid, dim3(256), 0, s, a, coeffs, work);
-        else if (RB == 1) {
+        else if (RB == 1 && split_pays(a)) {
             const dim3 g4(grid_for(a.n * kSplit));
             if (single) hipLaunchKernelGGL((k_scatter_split<T, true>), g4, dim3(256), 0, s, a, coeffs, work);
             else hipLaunchKernelGGL((k_scatter_split<T, false>), g4, dim3(256), 0, s, a, coeffs, work);
