@@ -50,17 +50,6 @@ size_t size_class(size_t b) {
     return (c + kMiB2 - 1) / kMiB2 * kMiB2;
 }
 
-// caller holds g_mu
-DevCache& cache_of(int dev) {
-    if ((int)g_cache.size() <= dev) g_cache.resize(dev + 1);
-    DevCache& C = g_cache[dev];
-    if (C.limit < 0) {
-        size_t fr = 0, tot = 0;
-        C.limit = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(tot / 4) : 0;
-    }
-    return C;
-}
-
 struct DeviceScope {
     int prev = -1;
     explicit DeviceScope(int dev) {
@@ -71,6 +60,18 @@ struct DeviceScope {
         if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
+
+// caller holds g_mu
+DevCache& cache_of(int dev) {
+    if ((int)g_cache.size() <= dev) g_cache.resize(dev + 1);
+    DevCache& C = g_cache[dev];
+    if (C.limit < 0) {
+        DeviceScope ds(dev);   // the memory size of this device, whichever is current
+        size_t fr = 0, tot = 0;
+        C.limit = hipMemGetInfo(&fr, &tot) == hipSuccess ? (int64_t)(tot / 4) : 0;
+    }
+    return C;
+}
 
 // caller holds g_mu; returns the bytes given back to the driver
 size_t trim_locked(int dev) {
@@ -163,15 +164,31 @@ hipError_t TableStager::add(DevMem& dst, const void* src, size_t bytes) {
     return hipSuccess;
 }
 
+namespace {
+// per thread and slot: the pinned buffer, and an event after the copies of the last flush that
+// have not been waited for yet
+thread_local void* t_pinned[2] = {nullptr, nullptr};
+thread_local size_t t_cap[2] = {0, 0};
+thread_local hipEvent_t t_done[2] = {nullptr, nullptr};
+thread_local bool t_pending[2] = {false, false};
+}  // namespace
+
+hipError_t TableStager::settle(Slot slot) {
+    if (!t_pending[slot]) return hipSuccess;
+    t_pending[slot] = false;
+    return hipEventSynchronize(t_done[slot]);
+}
+
 hipError_t TableStager::flush(hipStream_t st) {
-    thread_local void* pinned[2] = {nullptr, nullptr};
-    thread_local size_t cap[2] = {0, 0};
-    thread_local hipEvent_t done[2] = {nullptr, nullptr};   // copies of the slot's last flush
+    void** pinned = t_pinned;
+    size_t* cap = t_cap;
+    hipEvent_t* done = t_done;
     if (items.empty()) return hipSuccess;
-    if (done[slot]) {
-        hipError_t e = hipEventSynchronize(done[slot]);
+    {
+        hipError_t e = settle(slot);
         if (e != hipSuccess) return e;
-    } else {
+    }
+    if (!done[slot]) {
         hipError_t e = hipEventCreateWithFlags(&done[slot], hipEventDisableTiming);
         if (e != hipSuccess) return e;
     }
@@ -191,6 +208,7 @@ hipError_t TableStager::flush(hipStream_t st) {
     }
     hipError_t e = hipEventRecord(done[slot], st);
     if (e != hipSuccess) return e;
+    t_pending[slot] = true;
     items.clear();
     host.clear();
     return hipSuccess;

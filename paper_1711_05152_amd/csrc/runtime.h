@@ -84,14 +84,17 @@ struct DevMem {
 // add() allocates the device buffer and appends the bytes to a host list; flush() copies the list
 // into a pinned buffer owned by the calling thread (one per slot) and queues one asynchronous copy
 // per table on the stream, ordered before the kernels that read them.  A flush first waits for the
-// copies of the slot's previous flush (an event), so the pinned bytes outlive their copies.  The
-// device buffers must not be released before the copies have run (the stream is synchronised
-// before they go out of scope).
+// copies of the slot's previous flush (an event), so the pinned bytes outlive their copies; a
+// caller that destroys the stream it flushed on settles the slot first.  The device buffers must
+// not be released before the copies have run (the stream is synchronised before they go out of
+// scope).
 struct TableStager {
     enum Slot { PLAN = 0, DRIVER = 1 };
     explicit TableStager(Slot s) : slot(s) {}
     hipError_t add(DevMem& dst, const void* src, size_t bytes);
     hipError_t flush(hipStream_t st);
+    // wait for the copies of the slot's last flush on this thread (before their stream goes away)
+    static hipError_t settle(Slot slot);
     Slot slot;
     struct Item { DevMem* dst; size_t off, bytes; };
     std::vector<Item> items;

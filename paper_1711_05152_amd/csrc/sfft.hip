@@ -528,6 +528,7 @@ extern "C" mr1l_status sfft_detect(int d, const int32_t* lo, const int32_t* hi, 
         bool unc = false;
         mr1l_status res = run(C, cap, n_out, freqs_out, coeffs_out, &unc);
         hipStreamSynchronize(st);
+        (void)TableStager::settle(TableStager::DRIVER);   // its last copies ran on st
         hipStreamDestroy(st);
         if (stats) stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (res == MR1L_OK && unc) res = MR1L_WARN_UNCOVERED;

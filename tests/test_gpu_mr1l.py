@@ -328,3 +328,10 @@ def test_every_compiled_split_matches_oracle(lgn, dtype):
             _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, 2, None), "mr1l_fft_split")
     finally:
         _lib.lib().mr1l_fft_split(dt, lgn, -1, None)
+
+
+def test_graft_smoke_entry_point():
+    """The smoke entry point (one small forward + adjoint per precision against the oracle) runs."""
+    require_gpu()
+    import __graft_entry__
+    __graft_entry__.smoke()

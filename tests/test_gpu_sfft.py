@@ -219,3 +219,17 @@ def test_noise_success_rates_match_table_5_4():
         print(row, flush=True)
         assert _binomial_ok(round(row["success_rate"] * 20), 20, row["paper_success_rate"], slack=0.1), row
         assert row["max_rel_l2_error"] <= 3 * row["paper_max_rel_l2_error"], row
+
+
+def test_repeated_solves_reuse_staging_safely():
+    """Many solves in a row: each call creates and destroys its own stream, while the pinned
+    staging of step tables and the cached device blocks carry over between calls.  Every solve
+    returns the same result."""
+    require_gpu()
+    p = planted_c1()
+    first = None
+    for i in range(30):
+        res = _run(p, "c128" if i % 2 == 0 else "c64", 1e-12 if i % 2 == 0 else 1e-4, 50, 1)
+        if first is None:
+            first = res.freqs
+        assert np.array_equal(res.freqs, first), i
