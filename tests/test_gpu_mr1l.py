@@ -101,6 +101,43 @@ def test_standalone_full_size(dtype):
     assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0)
 
 
+MANY_LAT_CASES = [
+    # name, n, d, box, L, mlo, mhi: one transform, one right-hand side, Alg. 2's weights
+    ("L8_one_pass_half", 3000, 5, 20, 8, 3000, 6000),
+    ("L11_ragged_slots", 1777, 4, 30, 11, 1777, 3554),
+    ("L19_fourstep", 5001, 6, 25, 19, 5001, 10002),
+    ("L64_four_passes", 700, 3, 40, 64, 700, 1400),
+    ("L65_ragged_pass", 700, 3, 40, 65, 700, 1400),
+]
+
+
+@pytest.mark.parametrize("case", MANY_LAT_CASES, ids=[c[0] for c in MANY_LAT_CASES])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_many_lattices_plain_and_batched(case, dtype):
+    """One transform of 8 to 65 lattices (several passes of the gather's lattice slots): parity
+    with the oracle, and forward and adjoint bit-identical to the same transform twice inside a
+    batched plan (whose gather and scatter find each frequency's transform by search)."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import BatchedPlan
+    name, n, d, box, L, mlo, mhi = case
+    p = transform_problem(rng_for(307, zlib.crc32(name.encode())), n, d, box, L, mlo, mhi)
+    print(f"case {name} dtype {dtype}", flush=True)
+    plan = _plan(p, dtype)
+    c = plan.forward(_to(torch, p.samples, dtype))
+    yy = plan.adjoint(_to(torch, p.coeffs, dtype))
+    bp = BatchedPlan([(p.freqs, p.M, p.z), (p.freqs, p.M, p.z)], dtype=dtype, device=0)
+    cb = bp.forward(_to(torch, np.concatenate([p.samples, p.samples], axis=1), dtype))
+    yb = bp.adjoint(_to(torch, np.concatenate([p.coeffs, p.coeffs], axis=1), dtype))
+    torch.cuda.synchronize()
+    c_np, y_np = c.cpu().numpy(), yy.cpu().numpy()
+    assert_close(c_np, O.forward(p.freqs, p.M, p.z, p.samples), dtype, f"forward {name}")
+    assert_close(y_np, O.adjoint(p.freqs, p.M, p.z, p.coeffs), dtype, f"adjoint {name}")
+    sm = int(p.M.sum())
+    cb, yb = cb.cpu().numpy()[0], yb.cpu().numpy()[0]
+    assert np.array_equal(c_np[0], cb[:n]) and np.array_equal(c_np[0], cb[n:])
+    assert np.array_equal(y_np[0], yb[:sm]) and np.array_equal(y_np[0], yb[sm:])
+
+
 def test_standalone_dense_ndft_subset():
     """Coefficients of 64 covered frequencies of the full workload against the term-by-term sum
     of Alg. 2 (tier 0 of the oracle, no FFT)."""
