@@ -3,7 +3,7 @@
 //
 // Host side: L_max and lambda (Alg. 1 first two steps), the prime sizes p > lambda of P^I found by
 // trial division with a cached table of small primes, and the random generating vectors
-// (SplitMix64 Z stream keyed by (t, call, L)).  Device side, for rounds of up to eight trial
+// (SplitMix64 Z stream keyed by (t, call, L)).  Device side, for rounds of up to sixteen trial
 // lattices: the residues of all frequencies and the alias bitmaps of every lattice of the round
 // (one launch), then one pass that extends the running union of the unaliased sets and counts the
 // covered frequencies after each lattice of the round, and one device-to-host copy of those counts
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_trial_cover(const K* __restrict__ f, in
 
 // Batched trials (Alg. 1 itself): lattices i = 0..nk-1 of a round, generating vectors z[i][d],
 // sizes M[i]; bitmaps of lattice i at bm + i * 2 * wstride (seen, then multi at + wstride).
-constexpr int kSpec = 8;
+constexpr int kSpec = 16;
 struct TrialRound {
     int64_t M[kSpec];
     double invM[kSpec];

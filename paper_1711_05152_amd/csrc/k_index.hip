@@ -168,24 +168,24 @@ __global__ __launch_bounds__(256) void k_hist_merge(TxArgs a) {
     const uint32_t* p0 = a.part + a.rtiles[D.rt0].part;
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
         uint32_t sa = 0u, ma = 0u;
-        int i = 0;
-        for (; i + 8 <= D.rtn; i += 8) {
-            uint32_t ps[8], pm[8];
+        // all partials of a chunk in flight together (addresses clamped to the last partial, whose
+        // repeats are not counted)
+        constexpr int kMergeChunk = 16;
+        for (int i = 0; i < D.rtn; i += kMergeChunk) {
+            uint32_t ps[kMergeChunk], pm[kMergeChunk];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                ps[u] = p0[(int64_t)(i + u) * 2 * words + w];
-                pm[u] = p0[(int64_t)(i + u) * 2 * words + words + w];
+            for (int u = 0; u < kMergeChunk; ++u) {
+                const int64_t t = min(i + u, D.rtn - 1);
+                ps[u] = p0[t * 2 * words + w];
+                pm[u] = p0[t * 2 * words + words + w];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                ma |= pm[u] | (sa & ps[u]);
-                sa |= ps[u];
+            for (int u = 0; u < kMergeChunk; ++u) {
+                if (i + u < D.rtn) {
+                    ma |= pm[u] | (sa & ps[u]);
+                    sa |= ps[u];
+                }
             }
-        }
-        for (; i < D.rtn; ++i) {
-            const uint32_t ps = p0[(int64_t)i * 2 * words + w], pm = p0[(int64_t)i * 2 * words + words + w];
-            ma |= pm | (sa & ps);
-            sa |= ps;
         }
         a.bitmaps[D.bm_off + w] = sa;
         a.bitmaps[D.bm_off + words + w] = ma;
