@@ -120,14 +120,13 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
             else hits.push_back({&it->second, l});
         }
         if (miss.empty()) {
+            std::vector<CopySeg> segs;
             for (auto& h : hits) {
                 const LatDesc& D = P->hdesc[h.second];
-                hipError_t e = hipMemcpyAsync(filt + D.filt_off, h.first->buf.p, ((size_t)1 << D.lgN) * sizeof(cx<T>),
-                                              hipMemcpyDeviceToDevice, nullptr);
-                if (e != hipSuccess) return e;
+                segs.push_back(CopySeg{h.first->buf.p, filt + D.filt_off, ((uint64_t)1 << D.lgN) * sizeof(cx<T>)});
                 const_cast<FiltEntry*>(h.first)->used = ++g_fc_clock;
             }
-            return hipSuccess;
+            return copy_segments(segs.data(), (int)segs.size(), nullptr);
         }
     }
     hipError_t e = build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, filt, device, nullptr);

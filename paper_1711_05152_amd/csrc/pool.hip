@@ -165,8 +165,55 @@ hipError_t TableStager::add(DevMem& dst, const void* src, size_t bytes) {
 }
 
 namespace {
-// per thread and slot: the pinned buffer, and an event after the copies of the last flush that
-// have not been waited for yet
+constexpr int kCopySegs = 16;
+struct CopyBatch {
+    const char* src[kCopySegs];
+    char* dst[kCopySegs];
+    uint64_t bytes[kCopySegs];
+};
+
+// segment blockIdx.y of the batch; the blocks of a segment stride over it
+__global__ __launch_bounds__(256) void k_copy_segments(CopyBatch b) {
+    const int i = blockIdx.y;
+    const char* s = b.src[i];
+    char* d = b.dst[i];
+    const uint64_t n = b.bytes[i];
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t head = 0;
+    if ((((uintptr_t)s | (uintptr_t)d) & 15) == 0) {
+        head = n / 16 * 16;
+        for (uint64_t q = t; q < n / 16; q += step) ((uint4*)d)[q] = ((const uint4*)s)[q];
+    }
+    for (uint64_t q = head + t; q < n; q += step) d[q] = s[q];
+}
+}  // namespace
+
+hipError_t copy_segments(const CopySeg* segs, int n, hipStream_t st) {
+    for (int i0 = 0; i0 < n; i0 += kCopySegs) {
+        CopyBatch b{};
+        const int m = std::min(kCopySegs, n - i0);
+        uint64_t most = 0;
+        for (int i = 0; i < m; ++i) {
+            b.src[i] = (const char*)segs[i0 + i].src;
+            b.dst[i] = (char*)segs[i0 + i].dst;
+            b.bytes[i] = segs[i0 + i].bytes;
+            most = std::max(most, b.bytes[i]);
+        }
+        if (most == 0) continue;
+        // one 16-byte move per thread and sweep; at most 64 blocks per segment
+        const uint64_t blocks = std::min<uint64_t>(64, (most + 4095) / 4096);
+        hipLaunchKernelGGL(k_copy_segments, dim3((unsigned)blocks, (unsigned)m), dim3(256), 0, st, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+namespace {
+// per thread and slot: the pinned buffer, and an event after the copy of the last flush that has
+// not been waited for yet.  A kernel reads the pinned buffer, so it is allocated coherent and a
+// buffer that has grown too small is retired, not freed (process lifetime).
 thread_local void* t_pinned[2] = {nullptr, nullptr};
 thread_local size_t t_cap[2] = {0, 0};
 thread_local hipEvent_t t_done[2] = {nullptr, nullptr};
@@ -193,20 +240,20 @@ hipError_t TableStager::flush(hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     if (cap[slot] < host.size()) {
-        if (pinned[slot]) (void)hipHostFree(pinned[slot]);
         pinned[slot] = nullptr;
         cap[slot] = 0;
         const size_t want = std::max<size_t>(host.size(), (size_t)1 << 20);
-        hipError_t e = hipHostMalloc(&pinned[slot], want, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc(&pinned[slot], want, hipHostMallocCoherent | hipHostMallocPortable);
         if (e != hipSuccess) return e;
         cap[slot] = want;
     }
     std::memcpy(pinned[slot], host.data(), host.size());
-    for (const Item& it : items) {
-        hipError_t e = hipMemcpyAsync(it.dst->p, (char*)pinned[slot] + it.off, it.bytes, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipEventRecord(done[slot], st);
+    std::vector<CopySeg> segs;
+    segs.reserve(items.size());
+    for (const Item& it : items) segs.push_back(CopySeg{(const char*)pinned[slot] + it.off, it.dst->p, it.bytes});
+    hipError_t e = copy_segments(segs.data(), (int)segs.size(), st);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(done[slot], st);
     if (e != hipSuccess) return e;
     t_pending[slot] = true;
     items.clear();

@@ -80,14 +80,23 @@ struct DevMem {
     template <typename U> U* as() const { return (U*)p; }
 };
 
+// Segment copies in one launch per 16 segments: src and dst in device memory or in pinned,
+// device-accessible host memory, any alignment (16-byte moves where both ends allow).
+struct CopySeg {
+    const void* src;
+    void* dst;
+    uint64_t bytes;
+};
+hipError_t copy_segments(const CopySeg* segs, int n, hipStream_t st);
+
 // Small host tables (descriptors, generating vectors, tile lists) on their way to the device: each
 // add() allocates the device buffer and appends the bytes to a host list; flush() copies the list
-// into a pinned buffer owned by the calling thread (one per slot) and queues one asynchronous copy
-// per table on the stream, ordered before the kernels that read them.  A flush first waits for the
-// copies of the slot's previous flush (an event), so the pinned bytes outlive their copies; a
-// caller that destroys the stream it flushed on settles the slot first.  The device buffers must
-// not be released before the copies have run (the stream is synchronised before they go out of
-// scope).
+// into a pinned, device-accessible buffer owned by the calling thread (one per slot) and queues one
+// copy kernel that moves every table from there to its device buffer (one launch instead of one
+// copy call per table), ordered before the kernels that read them.  A flush first waits for the
+// copy of the slot's previous flush (an event), so the pinned bytes outlive their copy; a caller
+// that destroys the stream it flushed on settles the slot first.  The device buffers must not be
+// released before the copy has run (the stream is synchronised before they go out of scope).
 struct TableStager {
     enum Slot { PLAN = 0, DRIVER = 1 };
     explicit TableStager(Slot s) : slot(s) {}
