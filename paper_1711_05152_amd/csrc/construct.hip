@@ -235,10 +235,13 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
         // synchronisation.  Each draw depends only on its own stream key (t, call, L) and the
         // coverage after every lattice is recorded, so keeping the lattices up to the first that
         // completes the coverage (the later ones are discarded) is exactly the sequential result.
-        DevMem zk_dev, counts, bmr;
+        // one buffer per round, cleared by one memset: the kSpec coverage counts, then the alias
+        // bitmaps of the round's lattices
+        DevMem zk_dev, round;
         MR1L_HIP_TRY(zk_dev.alloc((size_t)kSpec * d * sizeof(int64_t)));
-        MR1L_HIP_TRY(counts.alloc((size_t)kSpec * sizeof(unsigned long long)));
-        MR1L_HIP_TRY(bmr.alloc((size_t)kSpec * 2 * words * sizeof(uint32_t)));
+        MR1L_HIP_TRY(round.alloc((size_t)kSpec * sizeof(unsigned long long) + (size_t)kSpec * 2 * words * sizeof(uint32_t)));
+        unsigned long long* counts = round.as<unsigned long long>();
+        uint32_t* bmr = (uint32_t*)(counts + kSpec);
         std::vector<int64_t> zk((size_t)kSpec * d);
         unsigned long long hc[kSpec];
         for (int call = 0; call < std::max(1, b); ++call) {
@@ -261,15 +264,15 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
                 }
                 MR1L_HIP_TRY(hipMemcpyAsync(zk_dev.p, zk.data(), (size_t)tr.nk * d * sizeof(int64_t),
                                             hipMemcpyHostToDevice, s));
-                MR1L_HIP_TRY(hipMemsetAsync(counts.p, 0, (size_t)tr.nk * sizeof(unsigned long long), s));
-                MR1L_HIP_TRY(hipMemsetAsync(bmr.p, 0, (size_t)tr.nk * 2 * words * sizeof(uint32_t), s));
+                MR1L_HIP_TRY(hipMemsetAsync(round.p, 0, (size_t)kSpec * sizeof(unsigned long long) +
+                                                            (size_t)tr.nk * 2 * words * sizeof(uint32_t), s));
                 hipLaunchKernelGGL(k_trial_hist_round<K>, dim3(blocks, tr.nk), dim3(256), 0, s, (const K*)f, n, d, n,
-                                   zk_dev.as<int64_t>(), tr, fast, bmr.as<uint32_t>(), words);
+                                   zk_dev.as<int64_t>(), tr, fast, bmr, words);
                 hipLaunchKernelGGL(k_trial_cover_round<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
-                                   zk_dev.as<int64_t>(), tr, fast, (const uint32_t*)bmr.p, words,
-                                   covered.as<uint8_t>(), counts.as<unsigned long long>());
+                                   zk_dev.as<int64_t>(), tr, fast, (const uint32_t*)bmr, words,
+                                   covered.as<uint8_t>(), counts);
                 MR1L_HIP_TRY(hipGetLastError());
-                MR1L_HIP_TRY(hipMemcpyAsync(hc, counts.p, (size_t)tr.nk * sizeof(unsigned long long),
+                MR1L_HIP_TRY(hipMemcpyAsync(hc, counts, (size_t)tr.nk * sizeof(unsigned long long),
                                             hipMemcpyDeviceToHost, s));
                 MR1L_HIP_TRY(hipStreamSynchronize(s));
                 for (int i = 0; i < tr.nk; ++i) {

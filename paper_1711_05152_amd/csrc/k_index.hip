@@ -467,26 +467,30 @@ __global__ void k_clear_bins(TxArgs a, cx<T>* work) {
         w[m] = {(T)0, (T)0};
 }
 
-// Fourier-matrix adjoint: bins[r_l(k)] += c_k over every lattice
+// Fourier-matrix adjoint: bins[r_l(k)] += c_k over every lattice, one thread per (lattice slot,
+// frequency) pair (slot u / n of frequency u mod n), so that few frequencies still keep many
+// residue loads and atomics in flight
 template <typename T, bool SINGLE, int RB>
 __global__ __launch_bounds__(256) void k_scatter_eval(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
     const int64_t rhs0 = (int64_t)blockIdx.y * RB;
     const int nr = (int)min((int64_t)RB, a.n_rhs - rhs0);
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pairs = a.n * (int64_t)a.max_nlat;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < pairs; u += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(u / a.n);
+        const int64_t g = u - (int64_t)j * a.n;
         const TxDesc t = get_tx<SINGLE>(a, g);
+        if (j >= t.nlat) continue;
+        const int64_t r = a.res32[(int64_t)j * a.rs + g];
         cx<T> v[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) v[q] = (q < nr) ? coeffs[(rhs0 + q) * a.n + g] : cx<T>{(T)0, (T)0};
-        for (int j = 0; j < t.nlat; ++j) {
-            const int64_t r = a.res32[(int64_t)j * a.rs + g];
-            cx<T>* dst = work + rhs0 * a.work_stride + a.desc[t.lat0 + j].work_off + r;
+        cx<T>* dst = work + rhs0 * a.work_stride + a.desc[t.lat0 + j].work_off + r;
 #pragma unroll
-            for (int q = 0; q < RB; ++q)
-                if (q < nr) {
-                    atomicAdd(&dst[q * a.work_stride].x, v[q].x);
-                    atomicAdd(&dst[q * a.work_stride].y, v[q].y);
-                }
-        }
+        for (int q = 0; q < RB; ++q)
+            if (q < nr) {
+                atomicAdd(&dst[q * a.work_stride].x, v[q].x);
+                atomicAdd(&dst[q * a.work_stride].y, v[q].y);
+            }
     }
 }
 
@@ -787,8 +791,9 @@ void launch_scatter(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, bool eval
     auto go = [&](auto RBc) {
         constexpr int RB = decltype(RBc)::value;
         const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
-        if (eval && single) hipLaunchKernelGGL((k_scatter_eval<T, true, RB>), grid, dim3(256), 0, s, a, coeffs, work);
-        else if (eval) hipLaunchKernelGGL((k_scatter_eval<T, false, RB>), grid, dim3(256), 0, s, a, coeffs, work);
+        const dim3 gpair(grid_for(a.n * (int64_t)a.max_nlat), grid.y);
+        if (eval && single) hipLaunchKernelGGL((k_scatter_eval<T, true, RB>), gpair, dim3(256), 0, s, a, coeffs, work);
+        else if (eval) hipLaunchKernelGGL((k_scatter_eval<T, false, RB>), gpair, dim3(256), 0, s, a, coeffs, work);
         else if (RB == 1 && split_pays(a)) {
             const dim3 g4(grid_for(a.n * kSplit));
             if (single) hipLaunchKernelGGL((k_scatter_split<T, true>), g4, dim3(256), 0, s, a, coeffs, work);
