@@ -151,6 +151,9 @@ void pool_free(void* p, size_t c, int dev) {
             return;
         }
     }
+    // work queued before the free may still use the block
+    DeviceScope ds(dev);
+    (void)hipDeviceSynchronize();
     (void)hipFree(p);
 }
 
