@@ -5,7 +5,8 @@
 // trial division with a cached table of small primes, and the random generating vectors
 // (SplitMix64 Z stream keyed by (t, call, L)).  Device side, for rounds of up to sixteen trial
 // lattices: the residues of all frequencies and the alias bitmaps of every lattice of the round
-// (one launch), then one pass that extends the running union of the unaliased sets and counts the
+// (LDS bitmaps per chunk of frequencies plus a merge; global atomics for lattices above 2^19
+// bins), then one pass that extends the running union of the unaliased sets and counts the
 // covered frequencies after each lattice of the round, and one device-to-host copy of those counts
 // (the stopping test of Alg. 1, applied lattice by lattice on the host).  The construction variant
 // with redraws keeps one lattice per round.
@@ -84,6 +85,78 @@ __global__ __launch_bounds__(256) void k_trial_hist_round(const K* __restrict__ 
         const uint32_t bit = 1u << (r & 31);
         const uint32_t old = atomicOr(b + (r >> 5), bit);
         if (old & bit) atomicOr(b + wstride + (r >> 5), bit);
+    }
+}
+
+// LDS form of the round's histograms (lattices of at most kTrialLdsWords bitmap words): one
+// workgroup per (chunk of frequencies, lattice i) counts its residues into LDS bitmaps over all
+// bins of the lattice and writes them out whole as a partial (lattice i, chunk c at
+// part + (i chunks + c) 2 wstride); k_trial_merge_round combines the partials of every lattice
+// (multi = some partial multi, or seen in two partials).  No global atomics, and the bitmaps need
+// no clearing.
+constexpr int kTrialThreads = 1024;
+constexpr int64_t kTrialLdsWords = (int64_t)1 << 14;   // 2 x 64 KiB of LDS: up to 2^19 bins
+
+template <typename K>
+__global__ __launch_bounds__(kTrialThreads) void k_trial_hist_lds(const K* __restrict__ f, int64_t nf, int d,
+                                                                  int64_t n, const int64_t* __restrict__ z,
+                                                                  TrialRound tr, int fast, int64_t chunk,
+                                                                  uint32_t* part, int64_t wstride) {
+    extern __shared__ uint32_t th_lds[];
+    const int i = blockIdx.y;
+    const int64_t M = tr.M[i];
+    const int words = (int)((M + 31) / 32);
+    uint32_t* seen = th_lds;
+    uint32_t* multi = th_lds + wstride;
+    for (int w = threadIdx.x; w < words; w += kTrialThreads) {
+        seen[w] = 0u;
+        multi[w] = 0u;
+    }
+    __syncthreads();
+    const int64_t g0 = (int64_t)blockIdx.x * chunk;
+    const int64_t g1 = min(n, g0 + chunk);
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kTrialThreads) {
+        const int64_t s = dot_kz<K>(f, nf, d, g, z + (int64_t)i * d);
+        const int64_t r = fast ? mod_fast(s, M, tr.invM[i]) : mod_exact(s, M);
+        const uint32_t bit = 1u << (r & 31);
+        const uint32_t old = atomicOr(&seen[r >> 5], bit);
+        if (old & bit) atomicOr(&multi[r >> 5], bit);
+    }
+    __syncthreads();
+    uint32_t* p = part + ((int64_t)i * gridDim.x + blockIdx.x) * 2 * wstride;
+    for (int w = threadIdx.x; w < words; w += kTrialThreads) {
+        p[w] = seen[w];
+        p[wstride + w] = multi[w];
+    }
+}
+
+// bitmaps of lattice blockIdx.y of the round (at bm + i 2 wstride) from its nchunks partials
+__global__ __launch_bounds__(256) void k_trial_merge_round(const uint32_t* __restrict__ part, int nchunks,
+                                                           TrialRound tr, uint32_t* bm, int64_t wstride) {
+    constexpr int kChunk = 16;   // partials whose loads are in flight together
+    const int i = blockIdx.y;
+    const int64_t words = (tr.M[i] + 31) / 32;
+    const uint32_t* p0 = part + (int64_t)i * nchunks * 2 * wstride;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t sa = 0u, ma = 0u;
+        for (int c0 = 0; c0 < nchunks; c0 += kChunk) {
+            uint32_t ps[kChunk], pm[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const int64_t c = min(c0 + u, nchunks - 1);   // clamped; repeats are not counted
+                ps[u] = p0[c * 2 * wstride + w];
+                pm[u] = p0[c * 2 * wstride + wstride + w];
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                if (c0 + u < nchunks) {
+                    ma |= pm[u] | (sa & ps[u]);
+                    sa |= ps[u];
+                }
+            }
+        }
+        bm[(int64_t)i * 2 * wstride + w] = sa;
+        bm[(int64_t)i * 2 * wstride + wstride + w] = ma;
     }
 }
 
@@ -237,11 +310,26 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
         // completes the coverage (the later ones are discarded) is exactly the sequential result.
         // one buffer per round, cleared by one memset: the kSpec coverage counts, then the alias
         // bitmaps of the round's lattices
-        DevMem zk_dev, round;
+        DevMem zk_dev, round, part;
         MR1L_HIP_TRY(zk_dev.alloc((size_t)kSpec * d * sizeof(int64_t)));
         MR1L_HIP_TRY(round.alloc((size_t)kSpec * sizeof(unsigned long long) + (size_t)kSpec * 2 * words * sizeof(uint32_t)));
         unsigned long long* counts = round.as<unsigned long long>();
         uint32_t* bmr = (uint32_t*)(counts + kSpec);
+        // LDS histograms where the bitmaps fit: chunks of at least 4096 frequencies, about 256
+        // workgroups per round
+        const bool lds = words <= kTrialLdsWords;
+        int chunks = 1;
+        int64_t chunk = n;
+        const size_t lds_bytes = 2 * (size_t)words * sizeof(uint32_t);
+        if (lds) {
+            chunks = (int)std::min<int64_t>(std::max<int64_t>(1, (n + 4095) / 4096), std::max(1, 256 / kSpec));
+            chunk = (n + chunks - 1) / chunks;
+            MR1L_HIP_TRY(part.alloc((size_t)kSpec * chunks * 2 * words * sizeof(uint32_t)));
+            if (lds_bytes > 65536)
+                MR1L_HIP_TRY(hipFuncSetAttribute((const void*)k_trial_hist_lds<K>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        }
+        const unsigned merge_x = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (words + 255) / 256));
         std::vector<int64_t> zk((size_t)kSpec * d);
         unsigned long long hc[kSpec];
         for (int call = 0; call < std::max(1, b); ++call) {
@@ -264,10 +352,19 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
                 }
                 MR1L_HIP_TRY(hipMemcpyAsync(zk_dev.p, zk.data(), (size_t)tr.nk * d * sizeof(int64_t),
                                             hipMemcpyHostToDevice, s));
-                MR1L_HIP_TRY(hipMemsetAsync(round.p, 0, (size_t)kSpec * sizeof(unsigned long long) +
-                                                            (size_t)tr.nk * 2 * words * sizeof(uint32_t), s));
-                hipLaunchKernelGGL(k_trial_hist_round<K>, dim3(blocks, tr.nk), dim3(256), 0, s, (const K*)f, n, d, n,
-                                   zk_dev.as<int64_t>(), tr, fast, bmr, words);
+                if (lds) {
+                    MR1L_HIP_TRY(hipMemsetAsync(round.p, 0, (size_t)kSpec * sizeof(unsigned long long), s));
+                    hipLaunchKernelGGL(k_trial_hist_lds<K>, dim3(chunks, tr.nk), dim3(kTrialThreads), lds_bytes, s,
+                                       (const K*)f, n, d, n, zk_dev.as<int64_t>(), tr, fast, chunk, part.as<uint32_t>(),
+                                       words);
+                    hipLaunchKernelGGL(k_trial_merge_round, dim3(merge_x, tr.nk), dim3(256), 0, s,
+                                       (const uint32_t*)part.p, chunks, tr, bmr, words);
+                } else {
+                    MR1L_HIP_TRY(hipMemsetAsync(round.p, 0, (size_t)kSpec * sizeof(unsigned long long) +
+                                                                (size_t)tr.nk * 2 * words * sizeof(uint32_t), s));
+                    hipLaunchKernelGGL(k_trial_hist_round<K>, dim3(blocks, tr.nk), dim3(256), 0, s, (const K*)f, n, d,
+                                       n, zk_dev.as<int64_t>(), tr, fast, bmr, words);
+                }
                 hipLaunchKernelGGL(k_trial_cover_round<K>, dim3(blocks), dim3(256), 0, s, (const K*)f, n, d, n,
                                    zk_dev.as<int64_t>(), tr, fast, (const uint32_t*)bmr, words,
                                    covered.as<uint8_t>(), counts);
