@@ -186,6 +186,22 @@ __device__ __forceinline__ unsigned int block_scan_u32(unsigned int v, unsigned 
     return r;
 }
 
+// fn(k, key) for this thread's positions k = threadIdx.x + j kSelThreads, with the loads of
+// kSelUnroll positions in flight together
+constexpr int kSelUnroll = 8;
+template <typename T, typename F>
+__device__ __forceinline__ void for_keys(const cx<T>* __restrict__ c, int64_t n, double delta2, F&& fn) {
+    int64_t k = threadIdx.x;
+    for (; k + (int64_t)(kSelUnroll - 1) * kSelThreads < n; k += (int64_t)kSelUnroll * kSelThreads) {
+        cx<T> v[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) v[u] = c[k + (int64_t)u * kSelThreads];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) fn(k + (int64_t)u * kSelThreads, sel_key(v[u], delta2));
+    }
+    for (; k < n; k += kSelThreads) fn(k, sel_key(c[k], delta2));
+}
+
 // One workgroup per right-hand side: flags[(rhs / rhs_per_group) * flags_stride + k] |= selected.
 template <typename T>
 __global__ __launch_bounds__(kSelThreads) void k_select(const cx<T>* __restrict__ coeffs, int64_t n, double delta2,
@@ -195,15 +211,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const cx<T>* __restrict_
     __shared__ unsigned int hist[256];
     __shared__ uint64_t sel_prefix;
     __shared__ int64_t sel_remaining;
+    __shared__ int64_t sel_equal;   // keys equal to the s-th largest (after the last pass)
     const int64_t rhs = blockIdx.x;
     const cx<T>* c = coeffs + rhs * n;
     uint8_t* f = flags + (rhs / rhs_per_group) * flags_stride;
     unsigned int local = 0;
-    for (int64_t k = threadIdx.x; k < n; k += kSelThreads) local += sel_key(c[k], delta2) != 0;
+    for_keys(c, n, delta2, [&](int64_t, uint64_t key) { local += key != 0; });
     const int64_t eligible = block_sum_u32(local, sh);
     if (eligible <= s) {
-        for (int64_t k = threadIdx.x; k < n; k += kSelThreads)
-            if (sel_key(c[k], delta2)) f[k] = 1;
+        for_keys(c, n, delta2, [&](int64_t k, uint64_t key) {
+            if (key) f[k] = 1;
+        });
         return;
     }
     // radix select of the s-th largest key, 8 bits per pass from the top
@@ -217,10 +235,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const cx<T>* __restrict_
         __syncthreads();
         const uint64_t prefix = sel_prefix;
         const uint64_t hi_mask = pass == 7 ? 0ull : (~0ull << (8 * (pass + 1)));
-        for (int64_t k = threadIdx.x; k < n; k += kSelThreads) {
-            const uint64_t key = sel_key(c[k], delta2);
+        for_keys(c, n, delta2, [&](int64_t, uint64_t key) {
             if ((key & hi_mask) == (prefix & hi_mask)) atomicAdd(&hist[(key >> (8 * pass)) & 255], 1u);
-        }
+        });
         __syncthreads();
         if (threadIdx.x == 0) {
             int64_t rem = sel_remaining, cum = 0;
@@ -231,11 +248,18 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const cx<T>* __restrict_
             }
             sel_remaining = rem - cum;
             sel_prefix = prefix | ((uint64_t)b << (8 * pass));
+            if (pass == 0) sel_equal = hist[b];
         }
         __syncthreads();
     }
     const uint64_t kstar = sel_prefix;
     const int64_t need_eq = sel_remaining;   // how many keys equal to kstar to take, lowest positions first
+    if (need_eq == sel_equal) {   // every key equal to kstar is taken: no ranking among them
+        for_keys(c, n, delta2, [&](int64_t k, uint64_t key) {
+            if (key >= kstar) f[k] = 1;
+        });
+        return;
+    }
     int64_t taken = 0;
     for (int64_t k0 = 0; k0 < n; k0 += kSelThreads) {
         const int64_t k = k0 + threadIdx.x;
@@ -259,12 +283,21 @@ __global__ __launch_bounds__(kSelThreads) void k_compact(const uint8_t* __restri
                                                          int64_t* count) {
     __shared__ unsigned int sh[kSelThreads];
     int64_t base = 0;
+    const bool vec = ((uintptr_t)flags & 15) == 0;   // 16 flags per 16-byte load
     for (int64_t k0 = 0; k0 < n; k0 += (int64_t)kSelThreads * kCompactPer) {
         const int64_t kb = k0 + (int64_t)threadIdx.x * kCompactPer;
         unsigned int bits = 0;
+        if (vec && kb + kCompactPer <= n) {
+            const uint4 q = *(const uint4*)(flags + kb);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int i = 0; i < kCompactPer; ++i)
-            if (kb + i < n && flags[kb + i]) bits |= 1u << i;
+            for (int i = 0; i < kCompactPer; ++i)
+                if ((w[i >> 2] >> (8 * (i & 3))) & 0xffu) bits |= 1u << i;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kCompactPer; ++i)
+                if (kb + i < n && flags[kb + i]) bits |= 1u << i;
+        }
         const unsigned int c = __popc(bits);
         const unsigned int incl = block_scan_u32(c, sh);
         int64_t pos = base + incl - c;
