@@ -80,6 +80,44 @@ __global__ void k_planted_1d(const int32_t* __restrict__ hf, int64_t s, const cx
     y[(int64_t)q * K + l] = make_cx<T>((T)acc.x, (T)acc.y);
 }
 
+// The same values for K <= kPlanted1dMaxK, one workgroup per job q: the phase of term h at point l
+// depends only on m = h_tc mod K, so the terms are first summed per class, B[m] = sum of w[q][h]
+// over h with h_tc = m mod K (ascending h), then y[q][l] = sum_m B[m] e^{2 pi i ((m l) mod K)/K}
+// (ascending m): K^2 phases instead of s K.
+constexpr int64_t kPlanted1dMaxK = 2048;   // B in LDS: 32 KiB
+template <typename T>
+__global__ __launch_bounds__(256) void k_planted_1d_bins(const int32_t* __restrict__ hf, int64_t s,
+                                                         const cx<double>* __restrict__ w,
+                                                         const int* __restrict__ comp, int64_t K,
+                                                         const uint64_t* __restrict__ keys, double sigma, cx<T>* y) {
+    __shared__ cx<double> B[kPlanted1dMaxK];
+    const int q = blockIdx.x;
+    const int kk = (int)K;
+    const int32_t* ht = hf + (int64_t)comp[q] * s;
+    const cx<double>* wq = w + (int64_t)q * s;
+    for (int m = threadIdx.x; m < kk; m += blockDim.x) {
+        cx<double> acc = {0.0, 0.0};
+        for (int64_t h = 0; h < s; ++h) {
+            int r = ht[h] % kk;
+            if (r < 0) r += kk;
+            if (r == m) acc = acc + wq[h];
+        }
+        B[m] = acc;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < kk; l += blockDim.x) {
+        cx<double> acc = {0.0, 0.0};
+        for (int m = 0; m < kk; ++m) {
+            const int qq = (int)(((int64_t)m * l) % kk);
+            double sn, cs;
+            sincospi(2.0 * (double)qq / (double)kk, &sn, &cs);
+            acc = acc + cmul(B[m], cx<double>{cs, sn});
+        }
+        if (sigma > 0.0) acc = acc + d_noise(keys[q], (uint64_t)l, sigma);
+        y[(int64_t)q * K + l] = make_cx<T>((T)acc.x, (T)acc.y);
+    }
+}
+
 // w[i][h] = c_h e^{2 pi i sum_{comp >= t} h_comp x~_comp^(i)}  (coefficients of the synthesis)
 template <typename T>
 __global__ void k_planted_wlat(const int32_t* __restrict__ hf, int64_t s, int d, int t, const cx<double>* __restrict__ c,
@@ -373,6 +411,15 @@ void sf_planted_w1d(const int32_t* hf, int64_t s, int d, const void* c, const do
 
 void sf_planted_1d(int dt, const int32_t* hf, int64_t s, const void* w, const int* comp, int njobs, int64_t K,
                    const uint64_t* keys, double sigma, void* y, hipStream_t st) {
+    if (K <= kPlanted1dMaxK && s > K) {   // per-class sums first
+        if (dt == MR1L_C128)
+            hipLaunchKernelGGL(k_planted_1d_bins<double>, dim3((unsigned)njobs), dim3(256), 0, st, hf, s,
+                               (const cx<double>*)w, comp, K, keys, sigma, (cx<double>*)y);
+        else
+            hipLaunchKernelGGL(k_planted_1d_bins<float>, dim3((unsigned)njobs), dim3(256), 0, st, hf, s,
+                               (const cx<double>*)w, comp, K, keys, sigma, (cx<float>*)y);
+        return;
+    }
     const dim3 grid((unsigned)((K + 255) / 256), (unsigned)njobs);
     if (dt == MR1L_C128)
         hipLaunchKernelGGL(k_planted_1d<double>, grid, dim3(256), 0, st, hf, s, (const cx<double>*)w, comp, K, keys,
