@@ -151,6 +151,25 @@ def test_construct_redraw_matches_oracle():
     assert hits > 0   # the variant actually redrew on these sets
 
 
+@pytest.mark.parametrize("n", [3000, 200_000, 270_000],
+                         ids=["lds_bitmaps", "lds_bitmaps_above_64KiB", "global_atomics_above_2p19_bins"])
+def test_construct_matches_oracle(n):
+    """mr1l_construct (Alg. 1 itself, rounds of trial lattices): lattice sizes, generating vectors
+    and the number of calls identical to the oracle's.  The sizes cover the three histogram paths
+    of a round: LDS bitmaps, LDS bitmaps beyond 64 KiB (lattices of 2^18..2^19 bins) and global
+    atomics (lattices above 2^19 bins, lambda = 2 (n - 1) > 2^19)."""
+    require_gpu()
+    from paper_1711_05152_amd.mr1l import mr1l_construct
+    from oracle import construct as Cn
+    from workloads import distinct_freqs
+    f = distinct_freqs(rng_for(342, n), n, 6, -40, 40)
+    print(f"construct n={n}", flush=True)
+    M, z, calls, unc = mr1l_construct(f, b=10, seed=41, t=3)
+    Mo, zo, cov, callso = Cn.construct_retry(f, b=10, seed=41, t=3)
+    assert np.array_equal(M, Mo) and np.array_equal(z, zo) and calls == callso
+    assert unc == 0 and cov
+
+
 def test_sfft_redraw_and_order_match_oracle():
     """sfft_detect with the redraw variant and with a component order: detected sets, per-step
     lattices, redraw counts and sample counts identical to the oracle's runs; a caller-supplied
