@@ -175,7 +175,7 @@ template <int ELEMS> struct Padded { static constexpr int v = ELEMS + (ELEMS >> 
 // thread.  The default 4096-element tile leaves C = 4096 / N1 columns, i.e. row segments shorter
 // than a 128-byte line once N1 > 256 (fp32) or N1 > 512 (fp64); such lengths take a tile of C =
 // 128 B / element columns instead, as far as LDS allows (2^14 fp32 / 2^13 fp64 elements, 148 KiB),
-// run by 1024 or 512 threads.  Stage 2 keeps 4096-element row tiles.
+// run by 1024 or 512 threads.  Stage 2 has row tiles of its own (RowTile).
 template <typename T, int LGN, int LG1>
 struct ColTile {
     static constexpr int LGN1 = LG1;
@@ -549,23 +549,38 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
 }
 
 // ---- four-step stage 2 -----------------------------------------------------------------------------
-// One tile = 2^(12 - LGN2) rows.  CONV: row DFT, multiply by the filter (conjugated for sign +1),
+// Row tiles: 2^TLG elements = 2^(TLG - LGN2) rows, at least two (a mirror pair) while LGN2 < 12,
+// run by NT threads of 16 values.  Rows of up to 2^10 points take 2048-element tiles: twice as
+// many workgroups as 4096-element ones, more than the chip holds at once, so the loads of some
+// overlap the arithmetic of others.
+constexpr int kP2TileLg = 11;
+template <int LGN, int LG1>
+struct RowTile {
+    static constexpr int LGN2 = LGN - LG1;
+    static constexpr int TLG = LGN2 + 1 > kP2TileLg ? kTileLg : kP2TileLg;
+    static constexpr int NT = (1 << TLG) / kVals;
+    static_assert(TLG >= LGN2 && TLG <= kTileLg, "row tile");
+};
+
+// One tile = 2^(TLG - LGN2) rows.  CONV: row DFT, multiply by the filter (conjugated for sign +1),
 // inverse row DFT (the forward's last stage and the inverse's first stage have the same radix and
 // hold the same elements, so the product never leaves the registers); else row DFT only.
 template <typename T, int LGN, int LG1, bool CONV>
-__global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
-                                                 const cx<T>* __restrict__ filt, int sign,
-                                                 const cx<T>* __restrict__ tw, int rot_in_base, int rot_out_base) {
-    constexpr int LGN1 = LG1, LGN2 = LGN - LGN1;
-    constexpr int LGR = kTileLg - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
-    constexpr int TPL_LG = LGN - kTileLg;
+__global__ __launch_bounds__((RowTile<LGN, LG1>::NT)) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
+                                                                const cx<T>* __restrict__ filt, int sign,
+                                                                const cx<T>* __restrict__ tw, int rot_in_base,
+                                                                int rot_out_base) {
+    using RT = RowTile<LGN, LG1>;
+    constexpr int LGN1 = LG1, LGN2 = LGN - LGN1, NT = RT::NT;
+    constexpr int LGR = RT::TLG - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
+    constexpr int TPL_LG = LGN - RT::TLG;
     constexpr int LR0 = stage_lr(LGN2, 0, true), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
     constexpr int NSI = n_stages(LGN2);
     constexpr int LRM = stage_lr(LGN2, NSI - 1, true), RM = 1 << LRM;   // forward last = inverse first
     constexpr int LGNBM = LGN2 - LRM;
     constexpr int LRL = stage_lr(LGN2, NSI - 1, false), RL = 1 << LRL, LGNBL = LGN2 - LRL;
     static_assert(stage_lr(LGN2, 0, false) == LRM, "the forward's last and the inverse's first stage must match");
-    __shared__ cx<T> lds[Padded<(1 << kTileLg)>::v];
+    __shared__ cx<T> lds[Padded<(1 << RT::TLG)>::v];
     const int li = blockIdx.x >> TPL_LG;
     const int t = blockIdx.x & ((1 << TPL_LG) - 1);
     const LatDesc D = a.desc[lat[li]];
@@ -588,18 +603,18 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int b, j;
-        bfly<LGNB0, ROWS, false>(u, b, j);
+        bfly<LGNB0, ROWS, false, NT>(u, b, j);
         const cx<T>* src = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[u * R0 + r] = src[(j + (r << LGNB0) + rin) & (N2 - 1)];
     }
-    fft_regs<T, LGN2, ROWS, N2, -1, true, false, false>(lds, v, tw);
+    fft_regs<T, LGN2, ROWS, N2, -1, true, false, false, NT>(lds, v, tw);
     if constexpr (CONV) {
         const cx<T>* f = filt + D.filt_off;
 #pragma unroll
         for (int u = 0; u < kVals / RM; ++u) {
             int b, j;
-            bfly<LGNBM, ROWS, false>(u, b, j);
+            bfly<LGNBM, ROWS, false, NT>(u, b, j);
             const int p = t * H + (b & (H - 1));
             const bool mirror = ROWS > 1 && b >= H && p != 0;
             const cx<T>* fr = f + ((int64_t)(mirror ? p : prow(b)) << LGN2);
@@ -610,11 +625,11 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
                 v[u * RM + r] = sign < 0 ? cmul(v[u * RM + r], fv) : cmulc(v[u * RM + r], fv);
             }
         }
-        fft_regs<T, LGN2, ROWS, N2, +1, false, false, false>(lds, v, tw);
+        fft_regs<T, LGN2, ROWS, N2, +1, false, false, false, NT>(lds, v, tw);
 #pragma unroll
         for (int u = 0; u < kVals / RL; ++u) {
             int b, j;
-            bfly<LGNBL, ROWS, false>(u, b, j);
+            bfly<LGNBL, ROWS, false, NT>(u, b, j);
             cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
             for (int r = 0; r < RL; ++r) dstp[(j + (r << LGNBL) + rout) & (N2 - 1)] = v[u * RL + r];
@@ -623,7 +638,7 @@ __global__ __launch_bounds__(kThreads) void k_p2(TxArgs a, const int* __restrict
 #pragma unroll
         for (int u = 0; u < kVals / RM; ++u) {
             int b, j;
-            bfly<LGNBM, ROWS, false>(u, b, j);
+            bfly<LGNBM, ROWS, false, NT>(u, b, j);
             cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
 #pragma unroll
             for (int r = 0; r < RM; ++r) dstp[j + (r << LGNBM)] = v[u * RM + r];
@@ -839,10 +854,11 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), (unsigned)a.n_rhs);
     with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
         constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
-        hipLaunchKernelGGL((k_p2<T, lg, l1, true>), grid, dim3(kThreads), 0, s, a, g.lat, work, filt, sign, tw, ri,
+        using RT = RowTile<lg, l1>;
+        const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG)), (unsigned)a.n_rhs);
+        hipLaunchKernelGGL((k_p2<T, lg, l1, true>), grid, dim3(RT::NT), 0, s, a, g.lat, work, filt, sign, tw, ri,
                            ro);
     });
 }
@@ -912,14 +928,15 @@ hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cons
                                    tmp, tw);
             });
         } else {
-            const dim3 grid((unsigned)(g.nlat << (g.lgN - kTileLg)), 1);
             with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
                 constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
                 using CT = ColTile<double, lg, l1>;
+                using RT = RowTile<lg, l1>;
                 const dim3 grid1((unsigned)(g.nlat << (lg - CT::TLG)), 1);
+                const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG)), 1);
                 hipLaunchKernelGGL((k_p1<double, lg, l1, 2>), grid1, dim3(CT::NT), 0, s, a, g.lat,
                                    (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw, 0);
-                hipLaunchKernelGGL((k_p2<double, lg, l1, false>), grid, dim3(kThreads), 0, s, a, g.lat, tmp,
+                hipLaunchKernelGGL((k_p2<double, lg, l1, false>), grid, dim3(RT::NT), 0, s, a, g.lat, tmp,
                                    (const cx<double>*)nullptr, -1, tw, -1, -1);
             });
         }
