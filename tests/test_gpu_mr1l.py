@@ -332,7 +332,8 @@ def test_large_bluestein_lengths(case, dtype):
     assert_close(yy.cpu().numpy(), O.adjoint(p.freqs, p.M, p.z, p.coeffs, "paper"), dtype, f"adjoint {name}")
 
 
-SPLIT_CASES = [(13, "c64"), (15, "c128"), (16, "c128"), (18, "c64"), (21, "c64"), (22, "c128")]
+SPLIT_CASES = [(13, "c64"), (13, "c128"), (15, "c64"), (15, "c128"), (16, "c128"), (18, "c64"), (21, "c64"),
+               (22, "c128")]
 
 
 @pytest.mark.parametrize("lgn,dtype", SPLIT_CASES, ids=[f"lg{a}_{b}" for a, b in SPLIT_CASES])
