@@ -550,9 +550,9 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
 
 // ---- four-step stage 2 -----------------------------------------------------------------------------
 // Row tiles: 2^TLG elements = 2^(TLG - LGN2) rows, at least two (a mirror pair) while LGN2 < 12,
-// run by NT threads of 16 values.  Rows of up to 2^10 points take 2048-element tiles: twice as
-// many workgroups as 4096-element ones, more than the chip holds at once, so the loads of some
-// overlap the arithmetic of others.
+// run by NT threads of 16 values.  Rows of up to 2^10 points take 2048-element tiles: workgroups
+// of two waves instead of four, so each barrier holds fewer waves and the loads of some workgroups
+// on a CU overlap the arithmetic of others (the same waves per CU either way).
 constexpr int kP2TileLg = 11;
 template <int LGN, int LG1>
 struct RowTile {
