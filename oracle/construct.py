@@ -137,18 +137,20 @@ def construct_retry(freqs, b: int, c: float = 2.0, gamma: float = 0.5, seed: int
 
 def b_rule(d: int, eps: float, gamma: float = 0.5) -> int:
     """Number of Alg. 1 calls from the lemma on repeated lattice searches (Sec. 4.1):
-    ceil((log 3 + log d - log eps)/|log gamma|)."""
+    ceil((log 3 + log d - log eps)/|log gamma|), the least b with gamma^b <= eps/(3d)."""
     return int(math.ceil((math.log(3) + math.log(d) - math.log(eps)) / abs(math.log(gamma))))
 
 
 def b_rule_r1(d: int, eps: float) -> int:
-    """b for the r = 1 setting of Sec. 4.3: ceil((log d - log eps)/log 2)."""
+    """b for the r = 1 setting of Sec. 4.3: ceil((log d - log eps)/log 2), the least b with
+    2^-b <= eps/d."""
     return int(math.ceil((math.log(d) - math.log(eps)) / math.log(2)))
 
 
 def r_rule(supp: int, d: int, eps: float) -> int:
-    """Detection iterations from the main theorem of Sec. 4.1:
-    ceil(2 |supp| (log 3 + log d + log |supp| - log eps))."""
+    """Detection iterations from the lemma and theorem of Sec. 4.1:
+    ceil(2 |supp| (log 3 + log d + log |supp| - log eps)); enough for the union bound
+    |supp| q^r <= eps/(3d) with q <= 3|supp|/(3|supp| + 2)."""
     return int(math.ceil(2 * supp * (math.log(3) + math.log(d) + math.log(supp) - math.log(eps))))
 
 

@@ -115,13 +115,93 @@ def test_construct_lattice_count_statistics():
     assert max(Ls) <= C.lmax(2000)
 
 
-def test_parameter_rules():
-    assert C.b_rule(5, 0.01) == math.ceil((math.log(3) + math.log(5) + math.log(100)) / math.log(2))
-    assert C.b_rule_r1(20, 1e-3) == math.ceil(math.log(20e3) / math.log(2))
-    assert C.r_rule(10, 5, 0.1) == math.ceil(20 * (math.log(3) + math.log(5) + math.log(10) + math.log(10)))
-    # sample bound of Sec. 3.2 with r = 1, s = 50, N = 8
-    Lt = math.ceil(2 * math.log(850) + 2 * math.log(2))
-    assert C.sample_bound(1, 50, 8) == 2 * Lt * max(2 * 849, 4 * Lt * math.log(Lt))
+def _least(pred) -> int:
+    v = 1
+    while not pred(v):
+        v += 1
+    return v
+
+
+def test_b_rule_is_the_least_count_the_lemma_needs():
+    """Lemma on repeated lattice searches (Sec. 4.1): one call of Alg. 1 fails with probability at
+    most gamma, so b independent calls all fail with probability at most gamma^b, and the rule's b
+    is the least count with gamma^b <= eps / (3d).  Checked against that defining inequality (not
+    the printed ceiling) on a grid, with slack only for the rounding of the logarithms."""
+    for d in (1, 2, 3, 5, 10, 20, 30, 64):
+        for eps in (0.9, 0.5, 0.1, 1e-2, 1e-3, 1e-6, 1e-9):
+            for gamma in (0.5, 0.25, 0.75, 0.9, 0.1):
+                target = eps / (3 * d)
+                x = math.log(target) / math.log(gamma)
+                if abs(x - round(x)) < 1e-9:
+                    continue   # exact boundary: the ceiling depends on the rounding of the logs
+                want = _least(lambda b: gamma ** b <= target)
+                assert C.b_rule(d, eps, gamma) == want, (d, eps, gamma)
+
+
+def test_single_alg1_call_fails_at_most_with_probability_gamma():
+    """The premise of the lemma on repeated lattice searches: one Alg. 1 call returns a
+    non-reconstructing lattice with probability at most gamma.  Over 240 seeded calls per setting
+    the failure frequency stays below gamma plus three binomial standard deviations."""
+    f = distinct_freqs(rng_for(230), 300, 4, -40, 40)
+    for c, gamma in ((2.0, 0.5), (2.0, 0.9), (1.5, 0.75)):
+        fails = sum(not C.construct(f, c, gamma, seed=seed, t=2)[2] for seed in range(240))
+        assert fails / 240 <= gamma + 3 * math.sqrt(gamma * (1 - gamma) / 240), (c, gamma, fails)
+
+
+def test_b_rule_r1_is_the_least_count_of_the_r1_setting():
+    """Sec. 4.3 (coefficients whose real or imaginary parts share a sign, r = 1): b calls with
+    failure probability 1/2 each must leave at most eps / d, i.e. the least b with
+    2^-b <= eps / d."""
+    for d in (1, 2, 5, 10, 20, 64):
+        for eps in (0.9, 0.5, 0.1, 1e-3, 1e-8):
+            x = math.log(eps / d) / math.log(0.5)
+            if abs(x - round(x)) < 1e-9:
+                continue
+            want = _least(lambda b: 0.5 ** b <= eps / d)
+            assert C.b_rule_r1(d, eps) == want, (d, eps)
+
+
+def test_r_rule_meets_the_union_bound_of_the_lemma():
+    """Lemma on the detection iterations (Sec. 4.1): a support frequency is missed by one iteration
+    with probability at most q <= 3S / (3S + 2) (S = |supp p^|, threshold at most a third of the
+    smallest coefficient), and the union bound needs S q^r <= eps / (3d).  The rule's r must reach
+    the least r with that property (dropping the log 3 or the factor 2 fails at S = 1) and exceed
+    it by at most the factor 2S (log(3S + 2) - log(3S)) < 4/3 + 1/S of the proof's last estimate."""
+    for S in (1, 2, 3, 10, 50, 1000):
+        q = 3.0 * S / (3.0 * S + 2.0)
+        for d in (1, 2, 5, 10, 30):
+            for eps in (0.5, 0.1, 1e-3, 1e-6):
+                target = eps / (3 * d)
+                need = _least(lambda r: S * q ** r <= target)
+                got = C.r_rule(S, d, eps)
+                assert got >= need, (S, d, eps, got, need)
+                assert got <= (4.0 / 3.0 + 1.0 / S) * need + 2, (S, d, eps, got, need)
+
+
+def _nth_prime_above(lam_value: float, count: int) -> int:
+    p, found = int(math.floor(lam_value)) + 1, 0
+    while True:
+        if C.is_prime(p):
+            found += 1
+            if found == count:
+                return p
+        p += 1
+
+
+def test_sample_bound_dominates_its_lattices():
+    """Sec. 3.2: with |J_t| <= m = r s (2N+1) candidates, Alg. 1 (c = 2, gamma = 1/2) draws at most
+    L~ = L_max(m) lattices whose prime sizes are the first L~ primes above lambda = 2(m - 1), each
+    below 2 max{2(m - 1), 4 L~ ln L~}; the bound 2 L~ max{...} therefore covers L~ times the L~-th
+    such prime.  Checked by trial division for a range of m (a factor 2 dropped from the bound, or
+    L~ not equal to Alg. 1's L_max, fails)."""
+    for r, s, N in ((1, 1, 0), (1, 1, 1), (1, 3, 2), (2, 5, 3), (1, 50, 8), (3, 40, 16), (1, 1000, 32),
+                    (5, 1000, 32)):
+        m = r * s * (2 * N + 1)
+        Lt = C.lmax(m, 2.0, 0.5)
+        assert Lt == math.ceil(2 * math.log(m) + 2 * math.log(2) - 1e-12)
+        pL = _nth_prime_above(C.lam(m, 2.0), Lt)
+        assert pL < 2 * max(2 * (m - 1), 4 * Lt * math.log(Lt)) or m == 1
+        assert C.sample_bound(r, s, N) >= Lt * pL, (r, s, N)
 
 
 # ---- selection -----------------------------------------------------------------------------------
@@ -270,6 +350,9 @@ def test_sample_count_matches_table_5_1():
         assert np.array_equal(res.freqs, p.freqs[order])
         errs.append(np.linalg.norm(res.coeffs - p.coeffs[order]) / np.linalg.norm(p.coeffs))
         counts.append(res.samples)
+        bound = C.sample_bound(1, 1000, 32)   # Sec. 3.2, per dimension step and iteration
+        for st in res.steps[1:]:
+            assert 1 - st["L"] + st["sumM"] < bound, (st["L"], st["sumM"], bound)
     assert max(errs) < 2e-15
     assert abs(max(counts) - gold[5]) <= 0.15 * gold[5], counts
 
