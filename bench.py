@@ -22,6 +22,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The CPU oracle legs run in spawned worker processes with one BLAS / OpenMP thread each (set here,
+# before numpy is imported anywhere in this process, and inherited by every worker).
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+    os.environ[_v] = "1"
+
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_TFLOPS = 157.3     # MI355X published FP32 vector peak
 FP64_VECTOR_TFLOPS = 78.6
@@ -32,7 +37,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="budget of each standalone-workload leg of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
@@ -415,6 +421,327 @@ def extra_autograd(steps: int):
             "loss_monotone": all(b <= a for a, b in zip(losses, losses[1:]))}
 
 
+# ---- CPU oracle baseline -----------------------------------------------------------------------------
+# The oracle as it stands (FP64 NumPy, tier 1) on the host cores, in spawned worker processes with one
+# thread each: a single-core leg (one worker, the paper's one-thread protocol) and an all-core leg
+# (a pool over lattices or transforms, one process per core of the allowed set).  Every worker builds
+# the seeded workloads itself; nothing GPU-side runs in them.
+_CPU_STATE: dict = {}
+
+
+def _cpu_c2():
+    if "c2" not in _CPU_STATE:
+        from workloads import standalone_c2
+        _CPU_STATE["c2"] = standalone_c2()
+    return _CPU_STATE["c2"]
+
+
+def _cpu_c2_pairs(seconds: float):
+    """Single core: forward + adjoint of the standalone workload, repeated for ``seconds``."""
+    from oracle import mr1l as O
+    p = _cpu_c2()
+    iters, t0 = 0, time.perf_counter()
+    while True:
+        O.forward(p.freqs, p.M, p.z, p.samples)
+        O.adjoint(p.freqs, p.M, p.z, p.coeffs)
+        iters += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    return iters, (time.perf_counter() - t0) / iters
+
+
+def _cpu_c2_alias(l: int):
+    from oracle import mr1l as O
+    p = _cpu_c2()
+    return O.unaliased_sets(p.freqs, p.M[l:l + 1], p.z[l:l + 1])[1][0]
+
+
+def _cpu_c2_fwd(l: int):
+    """Lattice l's term of Alg. 2: DFT_{M_l}(y_l)/M_l at the residues of I_l (0 elsewhere)."""
+    from oracle import mr1l as O
+    p = _cpu_c2()
+    off = O.sample_offsets(p.M)
+    return O.forward(p.freqs, p.M[l:l + 1], p.z[l:l + 1], p.samples[0, off[l]:off[l + 1]])
+
+
+def _cpu_c2_adj(args):
+    """Lattice l's slice of the adjoint for coefficients already divided by counter_k."""
+    from oracle import mr1l as O
+    l, cprime = args
+    p = _cpu_c2()
+    return O.adjoint(p.freqs, p.M[l:l + 1], p.z[l:l + 1], cprime)
+
+
+def _cpu_c2_pair_pool(pool):
+    """One forward + adjoint of the standalone workload with the lattices spread over the pool:
+    alias sets per lattice, lattice terms summed in ascending l and divided by counter_k (forward);
+    alias sets again, then each lattice's slice (adjoint)."""
+    import numpy as np
+    p = _cpu_c2()
+    L = len(p.M)
+    uniq = pool.map(_cpu_c2_alias, range(L))
+    counter = np.sum(uniq, axis=0)
+    terms = pool.map(_cpu_c2_fwd, range(L))
+    c = np.zeros(p.n, np.complex128)
+    for t in terms:
+        c += t
+    cov = counter > 0
+    c[cov] /= counter[cov]
+    c[~cov] = 0.0
+    uniq = pool.map(_cpu_c2_alias, range(L))
+    counter = np.sum(uniq, axis=0)
+    cp = np.where(counter > 0, p.coeffs[0] / np.maximum(counter, 1), 0.0)
+    y = np.concatenate(pool.map(_cpu_c2_adj, [(l, cp) for l in range(L)]))
+    return c, y
+
+
+class _TimedBlackBox:
+    """The oracle's planted black box with the time spent sampling accumulated (the paper reports
+    its solve times without it)."""
+
+    def __init__(self, bb):
+        self.bb, self.d, self.seconds = bb, bb.d, 0.0
+
+    def sample_1d(self, *a, **k):
+        t0 = time.perf_counter()
+        y = self.bb.sample_1d(*a, **k)
+        self.seconds += time.perf_counter() - t0
+        return y
+
+    def sample_lattice(self, *a, **k):
+        t0 = time.perf_counter()
+        y = self.bb.sample_lattice(*a, **k)
+        self.seconds += time.perf_counter() - t0
+        return y
+
+
+def _cpu_solve(case: str):
+    """One oracle solve (Alg. 3) of the plain (d = 5) or at-scale (d = 20) workload."""
+    from oracle.sfft import PlantedBlackBox, sfft
+    from workloads import planted_c1, planted_c3
+    if case == "d5_box8_s50_r1":
+        p, kw = planted_c1(), dict(delta=1e-12, s=50, r=1, seed=1711051521)
+    else:
+        p = planted_c3(1e-2 if case.endswith("sigma1e-2") else 0.0)
+        kw = dict(delta=1e-3, s=1000, r=5, seed=1711051523)
+    bb = _TimedBlackBox(PlantedBlackBox(p.freqs, p.coeffs, p.sigma, p.noise_seed))
+    t0 = time.perf_counter()
+    res = sfft(p.lo, p.hi, bb, kw["delta"], kw["s"], kw["s"], r=kw["r"], b=10, seed=kw["seed"])
+    total = time.perf_counter() - t0
+    return {"s_total": total, "s_excl_sampling": total - bb.seconds, "s_sampling": bb.seconds,
+            "detected": int(res.freqs.shape[0]), "samples": int(res.samples)}
+
+
+_C4_SUBSET = 16
+
+
+def _cpu_c4_problem(b: int):
+    key = ("c4", b)
+    if key not in _CPU_STATE:
+        import numpy as np
+        from workloads import batched_c4, cn01, rng_for
+        q = batched_c4(count=_C4_SUBSET, with_data=False)[b]
+        rng = rng_for(4, 1000 + b)
+        _CPU_STATE[key] = (q, cn01(rng, (int(q.M.sum()),)), cn01(rng, (q.n,)))
+    return _CPU_STATE[key]
+
+
+def _cpu_c4_pair(b: int):
+    """Forward + adjoint of transform b of the 512-transform batch (the first 16 are the subset)."""
+    from oracle import mr1l as O
+    q, y, c = _cpu_c4_problem(b)
+    t0 = time.perf_counter()
+    O.forward(q.freqs, q.M, q.z, y)
+    O.adjoint(q.freqs, q.M, q.z, c)
+    return q.n, time.perf_counter() - t0
+
+
+_C5_LATS = 2
+
+
+def _cpu_c5_part(l: int):
+    """Lattice l's share of one right-hand side of a gradient step of the least-squares workload:
+    synthesis A_l c, weighted residual (1/M_l)(A_l c - y_l), and A_l^* of it (Fourier-matrix
+    weighting)."""
+    import numpy as np
+    from oracle import mr1l as O
+    if "c5" not in _CPU_STATE:
+        from workloads import cn01, lsq_c5, rng_for
+        freqs, M, z, _ = lsq_c5()
+        _CPU_STATE["c5"] = (freqs, M, z, cn01(rng_for(5, 1000), (freqs.shape[0],)))
+    freqs, M, z, c = _CPU_STATE["c5"]
+    rng = np.random.default_rng(l)
+    y = rng.standard_normal(int(M[l])) + 1j * rng.standard_normal(int(M[l]))
+    t0 = time.perf_counter()
+    s_l = O.adjoint(freqs, M[l:l + 1], z[l:l + 1], c, "eval")
+    r_l = (s_l - y) / float(M[l])
+    O.forward(freqs, M[l:l + 1], z[l:l + 1], r_l, "eval")
+    return time.perf_counter() - t0
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(seconds: float):
+    """All CPU oracle figures of the bench line (see the module docstring for the workloads)."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import mr1l as O
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    P = max(1, min(16, allowed))
+    ctx = mp.get_context("spawn")
+    out = {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(), "cores_allowed": allowed,
+           "threads_per_process": 1}
+    with ctx.Pool(P) as pool:
+        # the headline single-core leg alone, then the other single-core legs side by side (one
+        # process each): the two d = 20 solves, the d = 5 solve, the batch and gradient-step subsets
+        iters, t_pair = pool.apply_async(_cpu_c2_pairs, (seconds,)).get()
+        jobs = {name: pool.apply_async(_cpu_solve, (name,))
+                for name in ("d20_box32_s1000_r5", "d20_box32_s1000_r5_sigma1e-2", "d5_box8_s50_r1")}
+        c4_one = pool.apply_async(_cpu_c4_all, ())
+        c5_one = pool.apply_async(_cpu_c5_sequential, ())
+        n4, t4 = c4_one.get()
+        t5 = c5_one.get()
+        solves = {k: j.get() for k, j in jobs.items()}
+        _progress("cpu oracle single-core legs done")
+        # all-core legs (the pool is idle now)
+        p = _cpu_c2()
+        c, y = _cpu_c2_pair_pool(pool)          # warm-up and check against the oracle's own call
+        assert np.allclose(c, O.forward(p.freqs, p.M, p.z, p.samples)[0], atol=1e-12)
+        assert np.allclose(y, O.adjoint(p.freqs, p.M, p.z, p.coeffs)[0], atol=1e-12)
+        k, t0 = 0, time.perf_counter()
+        while True:
+            _cpu_c2_pair_pool(pool)
+            k += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        t_pair_all = (time.perf_counter() - t0) / k
+        t0 = time.perf_counter()
+        r4 = pool.map(_cpu_c4_pair, range(_C4_SUBSET))
+        t4_all = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        nl5 = min(P, 20)
+        pool.map(_cpu_c5_part, range(nl5))
+        t5_all = time.perf_counter() - t0
+        _progress("cpu oracle all-core legs done")
+    n = _cpu_c2().n
+    out["standalone"] = {
+        "single_core": {"freqs_per_s": n / t_pair, "s_per_pair": t_pair, "pairs": iters},
+        "all_cores": {"freqs_per_s": n / t_pair_all, "s_per_pair": t_pair_all, "pairs": k, "processes": P,
+                      "split": "lattices over processes"}}
+    out["sfft_solves"] = solves
+    out["batched_512_subset"] = {
+        "sample": f"first {_C4_SUBSET} of the 512 transforms ({n4} frequencies), forward + adjoint each",
+        "single_core_freqs_per_s": n4 / t4, "all_cores_freqs_per_s": sum(r[0] for r in r4) / t4_all,
+        "all_cores_processes": P}
+    out["gd_step_subset"] = {
+        "sample": f"{_C5_LATS} of 20 lattices of 1 of 64 right-hand sides (single core), {nl5} lattices of 1 "
+                  f"right-hand side (all cores); scaled to the whole step",
+        "single_core_s_per_step_est": t5 * (20 / _C5_LATS) * 64,
+        "all_cores_s_per_step_est": t5_all * (20 / nl5) * 64, "all_cores_processes": P}
+    return out, P, t_pair, t_pair_all
+
+
+def _cpu_c4_all():
+    tot_n, tot_t = 0, 0.0
+    for b in range(_C4_SUBSET):
+        nb, tb = _cpu_c4_pair(b)
+        tot_n += nb
+        tot_t += tb
+    return tot_n, tot_t
+
+
+def _cpu_c5_sequential():
+    return sum(_cpu_c5_part(l) for l in range(_C5_LATS))
+
+
+def measure_standalone(p, dtype: str, steps: int, warmup: int) -> dict:
+    """Forward + adjoint steps of one plan of the standalone workload: the headline loop (HIP events
+    on the launch stream around all steps), the plan-cached loop, and a loop with the library's
+    per-stage events (its own step time reported beside the plain one)."""
+    import torch
+    from paper_1711_05152_amd.mr1l import Plan
+    dev = torch.device("cuda", 0)
+    tdt = {"c64": torch.complex64, "c128": torch.complex128}[dtype]
+    plan = Plan(p.freqs, p.M, p.z, dtype=dtype, weights="paper", n_rhs=1, device=0)
+    y = torch.from_numpy(p.samples).to(dev, tdt)
+    c_in = torch.from_numpy(p.coeffs).to(dev, tdt)
+    c_out = plan.empty_coeffs()
+    y_out = plan.empty_samples()
+
+    def step():
+        plan.forward(y, out=c_out)
+        plan.adjoint(c_in, out=y_out)
+
+    stream = torch.cuda.current_stream(dev)
+
+    def loop():
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_event, ms_wall = loop()
+    plan.cache_alias(True)
+    ms_cached, _ = loop()
+    plan.cache_alias(False)
+    plan.timing(True)
+    ms_event_timed, _ = loop()
+    stages = plan.timing_read()
+    plan.timing(False)
+    # timing_read covers the warm-up calls of the last loop as well
+    calls = steps + warmup
+    out = {"ms_event": ms_event, "ms_wall": ms_wall, "ms_cached": ms_cached, "ms_event_timed": ms_event_timed,
+           "per_launch": {k: v[0] / v[1] for k, v in stages.items()},
+           "per_step": {k: v[0] / calls for k, v in stages.items()},
+           "fft_lengths": [int(v) for v in plan.fft_lengths]}
+    plan.close()
+    return out
+
+
+def bluestein_alu(stage: str, ms: float, Ns, dtype: str):
+    """Nominal FFT flops (5 N log2 N per transform) a Bluestein stage launch executes, with the
+    four-step split the library uses for each length, over the launch time, against the vector peak
+    (diagnostic: Bluestein's padded lengths are not the method's algorithmic work)."""
+    import ctypes as C
+    from paper_1711_05152_amd import _lib
+    code = _lib.C64 if dtype == "c64" else _lib.C128
+    flops = 0.0
+    for N in Ns:
+        lg = int(round(math.log2(N)))
+        if stage == "bluestein_small":
+            flops += 2 * fft_flops(N)
+            continue
+        cur = C.c_int(0)
+        if _lib.lib().mr1l_fft_split(code, lg, 0, C.byref(cur)) != 0:
+            return None
+        lg1 = cur.value
+        if stage == "bluestein_p2":
+            flops += 2 * fft_flops(1 << (lg - lg1)) * (1 << lg1)
+        elif stage in ("bluestein_p1", "bluestein_p3"):
+            flops += fft_flops(1 << lg1) * (1 << (lg - lg1))
+        else:
+            return None
+    peak = FP32_VECTOR_TFLOPS if dtype == "c64" else FP64_VECTOR_TFLOPS
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "flops": flops}
+
+
 def _progress(msg: str) -> None:
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -433,10 +760,8 @@ def main():
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 (multi-GPU sharding "
                                    "is described in DESIGN.md, not implemented)"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
-    from paper_1711_05152_amd.mr1l import Plan
     from workloads import standalone_c2
 
     dev = torch.device("cuda", 0)
@@ -444,91 +769,24 @@ def main():
     p = standalone_c2()
     n, d, L = p.n, p.d, len(p.M)
     sumM = int(p.M.sum())
-    plan = Plan(p.freqs, p.M, p.z, dtype="c64", weights="paper", n_rhs=1, device=0)
-    y = torch.from_numpy(p.samples).to(dev, torch.complex64)
-    c_in = torch.from_numpy(p.coeffs).to(dev, torch.complex64)
-    c_out = plan.empty_coeffs()
-    y_out = plan.empty_samples()
-
-    def step():
-        plan.forward(y, out=c_out)
-        plan.adjoint(c_in, out=y_out)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_wall = (t1 - t0) * 1e3 / args.steps
-    ms_event = ev0.elapsed_time(ev1) / args.steps
-
-    # plan-cached variant: residues and alias bitmaps computed once and reused by every call
-    plan.cache_alias(True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev4 = torch.cuda.Event(enable_timing=True)
-    ev5 = torch.cuda.Event(enable_timing=True)
-    ev4.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev5.record(stream)
-    torch.cuda.synchronize()
-    ms_cached = ev4.elapsed_time(ev5) / args.steps
-    plan.cache_alias(False)
-    _progress(f"headline timed: {ms_event:.4f} ms/step, plan-cached {ms_cached:.4f} ms/step")
-
-    # per-stage device time: HIP events recorded by the library on the stream of each launch, over
-    # a second timed loop of the same steps (its own step time is reported beside the plain one)
-    plan.timing(True)
-    ev2 = torch.cuda.Event(enable_timing=True)
-    ev3 = torch.cuda.Event(enable_timing=True)
-    ev2.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev3.record(stream)
-    torch.cuda.synchronize()
-    ms_event_timed = ev2.elapsed_time(ev3) / args.steps
-    stages = plan.timing_read()
-    plan.timing(False)
-    per_launch = {k: v[0] / v[1] for k, v in stages.items()}
-    per_step = {k: v[0] / args.steps for k, v in stages.items()}
+    m64 = measure_standalone(p, "c64", args.steps, args.warmup)
+    _progress(f"headline timed: {m64['ms_event']:.4f} ms/step, plan-cached {m64['ms_cached']:.4f} ms/step")
+    ms_event, ms_wall, ms_cached = m64["ms_event"], m64["ms_wall"], m64["ms_cached"]
+    per_launch, per_step, Ns = m64["per_launch"], m64["per_step"], m64["fft_lengths"]
 
     # ---- roofline of the dominant kernel ------------------------------------------------------------
-    Ns = [int(v) for v in plan.fft_lengths]
+    # Every stage launch processes one direction of the whole transform (all L lattices), whose
+    # algorithmic bytes are 8 sum M_l (samples) + n d (packed int8 frequencies) + 8 n (coefficients).
+    alg_dir = 8 * sumM + n * d * 1 + 8 * n
     dom = max(per_step, key=per_step.get)
-    lg = [int(round(math.log2(N))) for N in Ns]
-    # four-step split of the library: N = N1 N2, N1 = 2^max(lgN - 12, min(lgN // 2, 8))
-    lg1 = [max(g - 12, min(g // 2, 8)) for g in lg]
-    if dom == "bluestein_p2":
-        # row FFTs (forward + inverse) of length N2 on N1 rows, per lattice, nominal 5 N log2 N each
-        flops = sum(2 * fft_flops(1 << (g - g1)) * (1 << g1) for g, g1 in zip(lg, lg1))
-    elif dom in ("bluestein_p1", "bluestein_p3"):
-        flops = sum(fft_flops(1 << g1) * (1 << (g - g1)) for g, g1 in zip(lg, lg1))
-    elif dom == "bluestein_small":
-        flops = sum(2 * fft_flops(N) for N in Ns)
-    else:
-        flops = None
     dom_ms = per_launch[dom]
-    if flops is not None:
-        achieved = flops / (dom_ms * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_TFLOPS, "traffic": stored_traffic(dom),
-                "avg_launch_ms": dom_ms, "work_per_launch": flops}
-    else:
-        nbytes = 8 * sumM + n * d + 8 * n
-        achieved = nbytes / (dom_ms * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom), "avg_launch_ms": dom_ms,
-                "work_per_launch": nbytes}
+    achieved = alg_dir / (dom_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom), "avg_launch_ms": dom_ms,
+            "work_per_launch": alg_dir,
+            "work_note": "algorithmic bytes of one direction (8 sum M + n d + 8 n), the units one launch of "
+                         "any stage processes; avg_launch_ms from HIP events around each launch",
+            "alu_diagnostic": bluestein_alu(dom, dom_ms, Ns, "c64")}
 
     # measured memory traffic (stored counter file of these sources) over each stage's launch time
     kernel_traffic = {}
@@ -536,12 +794,30 @@ def main():
         b = stored_traffic(k)
         if b is not None:
             kernel_traffic[k] = {"bytes_per_launch": b, "GBs": b / (t_ms * 1e-3) / 1e9,
-                                 "frac_hbm_peak": b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                 "frac_hbm_peak": b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "traffic_over_algorithmic": b / alg_dir}
 
     # end-to-end algorithmic bytes (samples + packed frequencies + coefficients, both directions)
-    alg_bytes = 2 * (8 * sumM + n * d * 1 + 8 * n)
+    alg_bytes = 2 * alg_dir
     e2e = {"alg_bytes_per_step": alg_bytes, "GBs": alg_bytes / (ms_event * 1e-3) / 1e9,
            "frac_hbm": alg_bytes / (ms_event * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if kernel_traffic and len(kernel_traffic) == len(per_launch):
+        step_traffic = sum(kernel_traffic[k]["bytes_per_launch"] * (per_step[k] / per_launch[k])
+                           for k in per_launch)
+        e2e["measured_traffic_per_step"] = step_traffic
+        e2e["traffic_over_algorithmic"] = step_traffic / alg_bytes
+
+    # complex128 companion of the same workload (the paper computes in IEEE double)
+    m128 = measure_standalone(p, "c128", args.steps, args.warmup)
+    alg_dir128 = 16 * sumM + n * d * 1 + 16 * n
+    dom128 = max(m128["per_step"], key=m128["per_step"].get)
+    c128 = {"value": n / (m128["ms_event"] * 1e-3), "unit": "freqs/s", "ms_per_step": m128["ms_event"],
+            "plan_cached_ms_per_step": m128["ms_cached"], "stages_ms_per_launch": m128["per_launch"],
+            "dominant_kernel": dom128,
+            "roofline_frac_hbm": alg_dir128 / (m128["per_launch"][dom128] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "alg_bytes_per_direction": alg_dir128,
+            "end_to_end_frac_hbm": 2 * alg_dir128 / (m128["ms_event"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    _progress(f"complex128 companion timed: {m128['ms_event']:.4f} ms/step")
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
@@ -554,22 +830,13 @@ def main():
     # ---- CPU oracle baseline ------------------------------------------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import mr1l as O
-        threads = 1
-        os.environ.setdefault("OMP_NUM_THREADS", "1")
-        iters = 0
-        tc0 = time.perf_counter()
-        while True:
-            O.forward(p.freqs, p.M, p.z, p.samples)
-            O.adjoint(p.freqs, p.M, p.z, p.coeffs)
-            iters += 1
-            if time.perf_counter() - tc0 > args.cpu_seconds:
-                break
-        tcpu = (time.perf_counter() - tc0) / iters
-        _progress(f"cpu oracle baseline: {iters} pairs, {tcpu:.3f} s each")
-        cpu = {"value": n / tcpu, "unit": "freqs/s", "cores": threads, "kind": "oracle",
-               "sample": f"{iters} forward+adjoint pairs of the same |I|=2^16 workload (numpy FFT tier, "
-                         f"FP64), {tcpu:.3f} s each"}
+        detail, P, t_one, t_all = cpu_baseline(args.cpu_seconds)
+        _progress(f"cpu oracle baseline: {t_one:.3f} s per pair on one core, {t_all:.3f} s on {P}")
+        cpu = {"value": n / t_all, "unit": "freqs/s", "cores": P, "kind": "oracle",
+               "sample": f"forward+adjoint pairs of the same |I|=2^16 workload for {args.cpu_seconds:.0f} s "
+                         f"(numpy FFT tier, FP64), lattices spread over {P} single-threaded processes; "
+                         f"one core: {n / t_one:.4g} freqs/s",
+               "single_core_value": n / t_one, **detail}
 
     line = {
         "metric": "mr1l-FFT freqs/s fwd+adj (|I|=2^16,d=10)",
@@ -580,7 +847,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_event,
         "ms_per_step_wall": ms_wall,
-        "ms_per_step_stage_timed": ms_event_timed,
+        "ms_per_step_stage_timed": m64["ms_event_timed"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -597,6 +864,7 @@ def main():
         "stages_ms_per_step": per_step,
         "stages_ms_per_launch": per_launch,
         "stages_measured_traffic": kernel_traffic or None,
+        "c128": c128,
         "cpu_baseline": cpu,
     }
     if not args.no_extras:

@@ -153,6 +153,14 @@ mr1l_status mr1l_cache_alias(mr1l_plan_t plan, int enable);
  * they are created.  Errors: MR1L_ERR_ARG for a length outside 13..24 or a split not compiled. */
 mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current);
 
+/* Bound of a plan's Bluestein work area (the intermediate of the prime-length DFTs, one region of
+ * sum_l N_l complex values per right-hand side).  Plans created from now on process
+ * floor(max_bytes / region bytes) right-hand sides per pass over the lattices (at least one) and
+ * loop over the passes within each call; results do not depend on the bound.  max_bytes > 0 sets
+ * it (process-wide), < 0 restores the default of 4 GiB, 0 only queries; ``current`` (optional)
+ * receives the bound in effect.  Never fails. */
+mr1l_status mr1l_work_limit(int64_t max_bytes, int64_t* current);
+
 /* Device-memory cache.  Every device buffer of the library (plan work areas, sparse-FFT steps)
  * comes from a per-device cache of size-classed blocks: a released block stays mapped and serves
  * later requests of its class, because allocating and freeing multi-GB regions through the driver

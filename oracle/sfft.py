@@ -44,7 +44,7 @@ import numpy as np
 
 from . import rng as R
 from .construct import construct_retry
-from .mr1l import forward, forward_direct, residues, sample_offsets, lattice_nodes
+from .mr1l import forward, forward_direct, residues, sample_offsets, lattice_nodes, unaliased_sets
 
 __all__ = ["PlantedBlackBox", "select_top", "decision_margin", "projection_1d", "sfft", "SfftResult"]
 
@@ -163,18 +163,21 @@ class SfftResult:
 
 def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = None,
          r: int = 1, b: int = 10, seed: int = 0, tier: int = 1, zero_anchors: bool = False,
-         redraw: int = 0, order=None, delta_1d: float | None = None) -> SfftResult:
+         redraw: int = 0, order=None, delta_1d: float | None = None, c: float = 2.0,
+         gamma: float = 0.5) -> SfftResult:
     """Alg. 3 on the box search space [box_lo, box_hi] (inclusive, per component).
     ``zero_anchors``: anchor components fixed to 0 instead of drawn (the r = 1 setting of the
     remark on coefficients with a common sign of real or imaginary part, Sec. 3.1).
     ``redraw``: construction variant (see ``oracle.construct``); ``order``: component order.
     ``delta_1d``: threshold of the 1-D detections (steps 1 and 2a) when it differs from
-    ``delta`` (the threshold-based truncation of Sec. 5.3 uses delta / 10 there)."""
+    ``delta`` (the threshold-based truncation of Sec. 5.3 uses delta / 10 there).
+    ``c``, ``gamma``: the parameters step 2b passes to Alg. 1 (Alg. 3 fixes 2 and 1/2).  Each step
+    records ``uncovered``, the frequencies of J_t in no I_l of the kept lattices (reading R4)."""
     if order is not None and list(order) != list(range(len(box_lo))):
         order = np.asarray(order, np.int64)
         assert sorted(order.tolist()) == list(range(len(box_lo))), "order must be a permutation"
         res = sfft(np.asarray(box_lo)[order], np.asarray(box_hi)[order], black_box.permuted(order), delta, s,
-                   s_local, r, b, seed, tier, zero_anchors, redraw, None, delta_1d)
+                   s_local, r, b, seed, tier, zero_anchors, redraw, None, delta_1d, c, gamma)
         orig = np.empty_like(res.freqs)
         orig[:, order] = res.freqs
         res.freqs = orig
@@ -221,7 +224,9 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
         J = np.concatenate([np.repeat(prev, len(It), axis=0),
                             np.tile(It, prev.shape[0]).reshape(-1, 1)], axis=1)
         cstats: dict = {}
-        M, z, covered, calls = construct_retry(J, b, seed=seed, t=t, redraw=redraw, stats=cstats)
+        M, z, covered, calls = construct_retry(J, b, c=c, gamma=gamma, seed=seed, t=t, redraw=redraw,
+                                               stats=cstats)
+        uncovered = int(np.count_nonzero(unaliased_sets(J, M, z)[2] == 0))
         r_t, s_t = (r, s_local) if t < d else (1, s)
         flags = np.zeros(J.shape[0], bool)
         for i in range(1, r_t + 1):
@@ -235,7 +240,8 @@ def sfft(box_lo, box_hi, black_box, delta: float, s: int, s_local: int | None = 
             res.samples += 1 - len(M) + int(np.sum(M))
             res.samples_full += int(np.sum(M))
         res.steps.append(dict(t=t, n_It=len(It), n_J=J.shape[0], L=len(M), sumM=int(np.sum(M)),
-                              calls=calls, covered=covered, M=M, z=z, redraws=cstats.get("redraws", 0)))
+                              calls=calls, covered=covered, uncovered=uncovered, M=M, z=z,
+                              redraws=cstats.get("redraws", 0)))
         prev = J[flags]
     res.freqs = prev.astype(np.int32)
     res.coeffs = last_coeffs[flags]

@@ -220,17 +220,7 @@ __global__ void k_pairs_congruent(const K* __restrict__ f, int64_t nf, int d, in
 }
 
 // ---- host helpers ----------------------------------------------------------------------------------
-static bool is_prime_u64(int64_t p) {
-    if (p < 2) return false;
-    if (p % 2 == 0) return p == 2;
-    for (int64_t q = 3; q * q <= p; q += 2)
-        if (p % q == 0) return false;
-    return true;
-}
-
-int64_t lmax_rule(int64_t n, double c, double gamma) {
-    return (int64_t)std::ceil(c * c / ((c - 1.0) * (c - 1.0)) * (std::log((double)n) - std::log(gamma)) / 2.0);
-}
+int64_t lmax_rule(int64_t n, double c, double gamma) { return host::lmax_rule(n, c, gamma); }
 
 template <typename K>
 static mr1l_status congruent_pair_exists(const void* f, int64_t nf, int d, int64_t n, int64_t p, bool* out,
@@ -265,24 +255,19 @@ static mr1l_status construct_t(int d, int64_t n, const void* f, int64_t maxabs, 
 
     // P^I_{lambda, L_max}: the L_max smallest primes p > lambda with k -> k mod p injective on I
     std::vector<int64_t> primes;
-    int64_t p = (int64_t)std::floor(lambda) + 1;
-    while ((int64_t)primes.size() < L_max) {
-        if (is_prime_u64(p)) {
-            bool ok = true;
-            if (p <= expansion) {   // otherwise distinct rows stay distinct modulo p
-                if (n > 65536) {
-                    set_error("prime-size injectivity check needs |I| <= 65536 when lambda < expansion of I");
-                    return MR1L_ERR_UNSUPPORTED;
-                }
-                bool clash = false;
-                mr1l_status st = congruent_pair_exists<K>(f, n, d, n, p, &clash, s);
-                if (st != MR1L_OK) return st;
-                ok = !clash;
-            }
-            if (ok) primes.push_back(p);
+    mr1l_status inj_status = MR1L_OK;
+    auto injective = [&](int64_t p) -> int {
+        if (p > expansion) return 1;   // distinct rows stay distinct modulo p
+        if (n > 65536) {
+            set_error("prime-size injectivity check needs |I| <= 65536 when lambda < expansion of I");
+            inj_status = MR1L_ERR_UNSUPPORTED;
+            return -1;
         }
-        ++p;
-    }
+        bool clash = false;
+        inj_status = congruent_pair_exists<K>(f, n, d, n, p, &clash, s);
+        return inj_status != MR1L_OK ? -1 : (clash ? 0 : 1);
+    };
+    if (host::prime_sizes(lambda, L_max, injective, primes) < 0) return inj_status;
     const int64_t maxM = primes.back();
     if (maxM >= ((int64_t)1 << 31)) {
         set_error("lattice sizes beyond 2^31 are not supported");

@@ -1,7 +1,8 @@
 // Schedule of the four-step Bluestein FFT: which compiled split each length uses.  The built-in
 // table is the one the tuning script measured (fft_schedule_table.h); mr1l_fft_split overrides an
 // entry for the process (the tuner itself times every candidate that way).  Plans read the
-// schedule when they are created.
+// schedule when they are created, and so they read the bound of their work area
+// (mr1l_work_limit), which decides how many right-hand sides one pass over the lattices holds.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -20,6 +21,9 @@ struct InitOverrides {
     }
 } g_init_overrides;
 
+constexpr int64_t kDefaultWorkLimit = (int64_t)4 << 30;
+std::atomic<int64_t> g_work_limit{kDefaultWorkLimit};
+
 int table_split(int dt, int lgN) {
     const int t = kTunedSplit[dt][lgN];
     return split_compiled(lgN, t) ? t : split_lgN1(lgN);
@@ -33,9 +37,19 @@ int fft_split(int dtype, int lgN) {
     return o >= 0 ? o : table_split(dt, lgN);
 }
 
+int64_t work_limit_bytes() { return g_work_limit.load(); }
+
 }  // namespace mr1l
 
 using namespace mr1l;
+
+extern "C" mr1l_status mr1l_work_limit(int64_t max_bytes, int64_t* current) {
+    clear_error();
+    if (max_bytes > 0) g_work_limit.store(max_bytes);
+    else if (max_bytes < 0) g_work_limit.store(kDefaultWorkLimit);
+    if (current) *current = g_work_limit.load();
+    return MR1L_OK;
+}
 
 extern "C" mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current) {
     clear_error();

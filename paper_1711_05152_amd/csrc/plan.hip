@@ -36,17 +36,11 @@ static int ceil_lg(int64_t v) {
 
 
 static mr1l_status check_distinct_rows(const int32_t* f, int64_t n, int d) {
-    std::vector<int64_t> idx(n);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-        return std::lexicographical_compare(f + a * d, f + a * d + d, f + b * d, f + b * d + d);
-    });
-    for (int64_t i = 1; i < n; ++i)
-        if (std::equal(f + idx[i - 1] * d, f + idx[i - 1] * d + d, f + idx[i] * d)) {
-            set_error("frequency rows " + std::to_string(idx[i - 1]) + " and " + std::to_string(idx[i]) +
-                      " are equal");
-            return MR1L_ERR_ARG;
-        }
+    int64_t a = 0, b = 0;
+    if (host::find_equal_rows(f, n, d, &a, &b)) {
+        set_error("frequency rows " + std::to_string(a) + " and " + std::to_string(b) + " are equal");
+        return MR1L_ERR_ARG;
+    }
     return MR1L_OK;
 }
 
@@ -392,10 +386,11 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->rhs_chunk = std::max<int64_t>(1, std::min<int64_t>(P->n_rhs, sp.max_work_bytes / per_rhs));
     }
     MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->rhs_chunk) * sizeof(cx<T>)));
-    // Fourier-matrix adjoint by counting sort where the pairs (k, l) are many (below that, a few
-    // atomics per pair are cheaper than the sort's launches)
-    P->args.bsort = sp.weights == MR1L_W_EVAL && (int64_t)n * max_nlat >= ((int64_t)1 << 16) &&
-                    (int64_t)n * max_nlat < ((int64_t)1 << 31) && P->sum_M < ((int64_t)1 << 31);
+    // Fourier-matrix adjoint by counting sort: every bin is summed by one thread in ascending k,
+    // so the synthesis is bit-reproducible from run to run (floating-point atomics are kept only for
+    // plans beyond the sort's 32-bit positions)
+    P->args.bsort = sp.weights == MR1L_W_EVAL && (int64_t)n * max_nlat < ((int64_t)1 << 31) &&
+                    P->sum_M < ((int64_t)1 << 31);
     if (P->args.bsort) {
         const int64_t nchunks = (P->sum_M + kScanChunk - 1) / kScanChunk;
         MR1L_HIP_TRY(P->bcnt.alloc((size_t)P->sum_M * sizeof(int32_t)));

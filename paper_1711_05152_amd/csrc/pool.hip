@@ -28,27 +28,12 @@
 namespace mr1l {
 namespace {
 
-struct DevCache {
-    std::multimap<size_t, void*> ready, pending;
-    size_t idle = 0;       // bytes held in ready + pending
-    int64_t limit = -1;    // cap on idle bytes; -1 until first use
-};
+// size classes and the ready / pending bookkeeping live in host_logic.h (host::BlockCache)
+using DevCache = host::BlockCache;
+using host::size_class;
 
 std::mutex g_mu;
 std::vector<DevCache> g_cache;
-
-size_t size_class(size_t b) {
-    constexpr size_t kMiB2 = (size_t)2 << 20;
-    if (b <= kMiB2) {
-        size_t c = 256;
-        while (c < b) c <<= 1;
-        return c;
-    }
-    const int k = 63 - __builtin_clzll((unsigned long long)b);     // 2^k <= b < 2^(k+1)
-    const size_t step = ((size_t)1 << k) / 8;
-    size_t c = (b + step - 1) / step * step;
-    return (c + kMiB2 - 1) / kMiB2 * kMiB2;
-}
 
 struct DeviceScope {
     int prev = -1;
@@ -79,16 +64,7 @@ size_t trim_locked(int dev) {
     if (C.ready.empty() && C.pending.empty()) return 0;
     DeviceScope ds(dev);
     (void)hipDeviceSynchronize();
-    size_t freed = 0;
-    for (auto* m : {&C.ready, &C.pending}) {
-        for (auto& kv : *m) {
-            (void)hipFree(kv.second);
-            freed += kv.first;
-        }
-        m->clear();
-    }
-    C.idle = 0;
-    return freed;
+    return C.release_all([](void* p, size_t) { (void)hipFree(p); });
 }
 
 }  // namespace
@@ -103,27 +79,15 @@ hipError_t pool_alloc(void** p, size_t bytes, int* dev_out, size_t* block_out) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         DevCache& C = cache_of(dev);
-        const size_t cmax = c + c / 2;
-        auto fit = [&](std::multimap<size_t, void*>& m) {
-            auto it = m.lower_bound(c);
-            return (it != m.end() && it->first <= cmax) ? it : m.end();
-        };
-        auto it = fit(C.ready);
-        if (it == C.ready.end() && fit(C.pending) != C.pending.end()) {
+        DevCache::Find r = C.take(c, p, block_out);
+        if (r == DevCache::NEEDS_DRAIN) {
             // every pending block becomes reusable once the device has drained
             e = hipDeviceSynchronize();
             if (e != hipSuccess) return e;
-            C.ready.insert(C.pending.begin(), C.pending.end());
-            C.pending.clear();
-            it = fit(C.ready);
+            C.drained();
+            r = C.take(c, p, block_out);
         }
-        if (it != C.ready.end()) {
-            *p = it->second;
-            *block_out = it->first;
-            C.idle -= it->first;
-            C.ready.erase(it);
-            return hipSuccess;
-        }
+        if (r == DevCache::HIT) return hipSuccess;
     }
     e = hipMalloc(p, c);
     if (e == hipErrorOutOfMemory) {
@@ -144,12 +108,7 @@ void pool_free(void* p, size_t c, int dev) {
     if (!p) return;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        DevCache& C = cache_of(dev);
-        if ((int64_t)(C.idle + c) <= C.limit) {
-            C.pending.insert({c, p});
-            C.idle += c;
-            return;
-        }
+        if (cache_of(dev).give_back(p, c)) return;
     }
     // work queued before the free may still use the block
     DeviceScope ds(dev);

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.h"
+#include "host_logic.h"
 #include "mr1l.h"
 
 namespace mr1l {
@@ -110,36 +111,11 @@ struct TableStager {
     std::vector<char> host;
 };
 
-// Counter-based SplitMix64 streams (published generator; the key derivation is this project's):
-//   key(seed, f1..fm): k = seed; k = mix64(k + GAMMA (f + 1)) for each field f
-//   draw(k, c) = mix64(k + GAMMA (c + 1))
-struct Rng {
-    static constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
-    static uint64_t mix64(uint64_t x) {
-        x ^= x >> 30;
-        x *= 0xBF58476D1CE4E5B9ull;
-        x ^= x >> 27;
-        x *= 0x94D049BB133111EBull;
-        x ^= x >> 31;
-        return x;
-    }
-    static uint64_t key(uint64_t seed, std::initializer_list<int64_t> fields) {
-        uint64_t k = seed;
-        for (int64_t f : fields) k = mix64(k + GAMMA * (uint64_t)(f + 1));
-        return k;
-    }
-    static uint64_t draw(uint64_t k, uint64_t c) { return mix64(k + GAMMA * (c + 1)); }
-    static double uniform01(uint64_t k, uint64_t c) { return (double)(draw(k, c) >> 11) * 0x1.0p-53; }
-    // unbiased integer in [0, M): rejection of draws below 2^64 mod M; advances *c
-    static uint64_t uniform_int(uint64_t k, uint64_t* c, uint64_t M) {
-        const uint64_t floor_reject = (0 - M) % M;   // == 2^64 mod M
-        for (;;) {
-            const uint64_t u = draw(k, (*c)++);
-            if (u >= floor_reject) return u % M;
-        }
-    }
-    enum Purpose : int64_t { Z = 1, ANCHOR1D = 2, ANCHOR = 3, NOISE = 4, ZREDRAW = 5 };
-};
+// Counter-based SplitMix64 streams of the method's random draws (host_logic.h).
+using host::Rng;
+
+// Bound of a plan's Bluestein work area in bytes (process-wide, mr1l_work_limit; default 4 GiB).
+int64_t work_limit_bytes();
 
 // Description of the transforms a plan holds.  A plain plan has one transform; a batched plan
 // stacks several independent ones (own frequencies, own lattices).
@@ -155,7 +131,7 @@ struct PlanSpec {
     int dev_ktype = K_I32;
     int64_t dev_maxabs = 0;            // max |k| of the device frequencies
     bool check_distinct = true;
-    int64_t max_work_bytes = (int64_t)4 << 30;   // bound of the Bluestein work area (rhs chunking)
+    int64_t max_work_bytes = work_limit_bytes();   // bound of the Bluestein work area (rhs chunking)
     // reuse the filter spectra of a plan with the same lattice sizes (same order) and dtype
     const struct Plan* share_filters = nullptr;
     // transforms

@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "memory_cache", "version"]
+__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "memory_cache", "work_limit", "version"]
 
 _DT = {"c64": (_lib.C64, torch.complex64), "c128": (_lib.C128, torch.complex128)}
 _W = {"paper": _lib.W_PAPER, "eval": _lib.W_EVAL}
@@ -36,6 +36,14 @@ def memory_cache(device: int = 0, max_idle_bytes: int = -1) -> int:
     set the cap on idle bytes (< 0 keeps it, 0 disables caching); returns the bytes released."""
     out = C.c_int64(0)
     check(lib().mr1l_memory_cache(int(device), int(max_idle_bytes), C.byref(out)), "mr1l_memory_cache")
+    return int(out.value)
+
+
+def work_limit(max_bytes: int = 0) -> int:
+    """mr1l_work_limit: bound of the Bluestein work area of plans created from now on (> 0 sets it,
+    < 0 restores the default, 0 queries); returns the bound in effect."""
+    out = C.c_int64(0)
+    check(lib().mr1l_work_limit(int(max_bytes), C.byref(out)), "mr1l_work_limit")
     return int(out.value)
 
 

@@ -164,11 +164,16 @@ def sfft_detect(lo, hi, *, planted=None, sampler=None, bspline: BsplineSum | Non
         def _cb(user, dd, n, nodes_ptr, values_ptr, stream):
             try:
                 dev = torch.device("cuda", device)
-                x = torch.as_tensor(_CudaArray(nodes_ptr, (n, dd), "<f8"), device=dev)
-                out = torch.as_tensor(_CudaArray(values_ptr, (n, 2), "<f8" if dtype == "c128" else "<f4"),
-                                      device=dev)
-                v = sampler(x).to(tdt)
-                out.copy_(torch.view_as_real(v))
+                # the library wrote the nodes on ``stream``: the caller's torch work is ordered
+                # after that by running on the same stream, whatever torch's current stream is
+                lib_stream = (torch.cuda.ExternalStream(stream, device=dev) if stream
+                              else torch.cuda.default_stream(dev))
+                with torch.cuda.stream(lib_stream):
+                    x = torch.as_tensor(_CudaArray(nodes_ptr, (n, dd), "<f8"), device=dev)
+                    out = torch.as_tensor(_CudaArray(values_ptr, (n, 2), "<f8" if dtype == "c128" else "<f4"),
+                                          device=dev)
+                    v = sampler(x).to(tdt)
+                    out.copy_(torch.view_as_real(v))
                 torch.cuda.synchronize(dev)
                 return 0
             except Exception:  # reported as MR1L_ERR_CALLBACK

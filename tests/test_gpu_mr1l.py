@@ -373,3 +373,37 @@ def test_graft_smoke_entry_point():
     require_gpu()
     import __graft_entry__
     __graft_entry__.smoke()
+
+
+@pytest.mark.parametrize("weights", ["paper", "eval"])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_rhs_chunking_matches_one_pass(weights, dtype):
+    """A work-area bound that holds three right-hand sides makes the plan loop over passes of 3, 3
+    and 1 of its 7 right-hand sides (offset chunks, a short last one; the Fourier-matrix adjoint
+    sums its bins per chunk after one counting sort): forward and adjoint are bit-identical to a
+    plan that does all seven in one pass, and agree with the oracle."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import work_limit
+    p = transform_problem(rng_for(951), 3000, 5, 16, 6, 3000, 9000, n_rhs=7)
+    one = _plan(p, dtype, weights)
+    esz = 8 if dtype == "c64" else 16
+    region = int(one.fft_lengths.sum()) * esz
+    default = work_limit(0)
+    try:
+        assert work_limit(3 * region + esz) == 3 * region + esz
+        chunked = _plan(p, dtype, weights)
+    finally:
+        assert work_limit(-1) == default
+    y = _to(torch, p.samples, dtype)
+    c = _to(torch, p.coeffs, dtype)
+    outs = []
+    for plan in (one, chunked):
+        outs.append((plan.forward(y).cpu().numpy(), plan.adjoint(c).cpu().numpy()))
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a.view(np.float32 if dtype == "c64" else np.float64),
+                              b.view(np.float32 if dtype == "c64" else np.float64))
+    c_ref = O.forward(p.freqs, p.M, p.z, p.samples, weights)
+    y_ref = O.adjoint(p.freqs, p.M, p.z, p.coeffs, weights)
+    assert_close(outs[1][0], c_ref, dtype, "chunked forward")
+    assert_close(outs[1][1], y_ref, dtype, "chunked adjoint")

@@ -5,14 +5,16 @@ oracle run with the same seed (same SplitMix64 streams on both sides); coefficie
 precision of the transforms.  The full-size d = 20 workload is checked through properties that
 hold at any size (exact support recovery, coefficient error against the planted values).
 """
+import importlib.util
 import math
+import os
 
 import numpy as np
 import pytest
 
 from gpu_util import require_gpu, assert_close
 from oracle.sfft import sfft as oracle_sfft, PlantedBlackBox
-from workloads import rng_for, random_planted, planted_c1, planted_c3
+from workloads import S0, rng_for, random_planted, planted_c1, planted_c3, sweep_t52, sweep_t54
 
 pytestmark = pytest.mark.gpu
 
@@ -114,20 +116,177 @@ def test_callback_sampler_matches_planted():
     assert np.array_equal(cb.freqs, p.freqs[_lex(p.freqs)])
 
 
+_GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden_module():
+    spec = importlib.util.spec_from_file_location(
+        "make_sfft_oracle_golden", os.path.join(_GOLDEN_DIR, "make_sfft_oracle_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _compare_with_golden(name, p, got, dtype, min_margin):
+    """The library's solve against the oracle's stored solve of the same inputs (written by
+    tests/golden/make_sfft_oracle_golden.py): detected set, per-step |I^(t)|, |J_t|, lattices,
+    sizes, Alg. 1 calls and uncovered counts, sample count (all exact) and coefficients (R15).
+    The oracle's smallest decision margin must leave room for the transform's rounding."""
+    gm = _golden_module()
+    g = np.load(gm.path(name))
+    assert str(g["digest"]) == gm.input_digest(p), "golden file was made from other inputs"
+    margin = float(g["margin"])
+    print(f"{name}: oracle decision margin {margin:.3e}", flush=True)
+    assert margin >= min_margin, f"oracle decision margin {margin:.3e} too close to rounding"
+    assert np.array_equal(got.freqs, g["freqs"]), (got.freqs.shape, g["freqs"].shape)
+    keys = [str(k) for k in g["step_keys"]]
+    st = got.stats
+    for row in g["steps"]:
+        step = dict(zip(keys, (int(v) for v in row)))
+        t = step["t"]
+        assert st["n_It"][t - 1] == step["n_It"], (name, t)
+        if t == 1:
+            continue
+        for k in ("n_J", "L", "sumM", "calls", "uncovered"):
+            assert st[k][t - 1] == step[k], (name, t, k, st[k][t - 1], step[k])
+    assert st["samples"] == int(g["samples"])
+    assert st["samples_full"] == int(g["samples_full"])
+    assert_close(got.coeffs, g["coeffs"], dtype, f"{name} coefficients vs oracle")
+
+
 @pytest.mark.parametrize("sigma", [0.0, 1e-2])
 def test_scale_d20_box32_s1000(sigma):
     """d = 20, box [-32,32]^20, s = 1000, |c| in [1,10], r = 5, delta = 1e-3, complex64 transforms:
-    exact support recovery (no false positives, no misses) and coefficient error against the
-    planted values within the noise level."""
+    the oracle's solve of the same inputs (stored) is reproduced exactly (set, every step's
+    lattices and counts, samples; coefficients within R15), the planted support is recovered
+    exactly and the coefficient error against the planted values stays within the noise level."""
     require_gpu()
     p = planted_c3(sigma)
     got = _run(p, "c64", 1e-3, 1000, 5, seed=1711051523)
+    _compare_with_golden("c3_sigma0" if sigma == 0 else "c3_sigma1e-2", p, got, "c64", 1e-2)
     order = _lex(p.freqs)
     assert np.array_equal(got.freqs, p.freqs[order])
     err = np.abs(got.coeffs - p.coeffs[order])
     print(f"sigma {sigma}: max coeff err {err.max():.3e}, samples {got.stats['samples']}, "
           f"ms {got.stats['ms_total']:.1f}", flush=True)
     assert err.max() <= (1e-4 * 10 if sigma == 0 else 1e-3)
+
+
+def test_table52_setting_matches_oracle():
+    """Setting of Table 5.2 (d = 5, N = 32, s = 1000, unit moduli, r = 2, delta = 0.1), complex128:
+    the solve reproduces the oracle's stored solve of the same instance exactly."""
+    require_gpu()
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = sweep_t52(0)
+    got = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=0.1, s=1000, r=2, b=10,
+                      seed=S0 + 52000, dtype="c128", cap=1000)
+    _compare_with_golden("t52_r2_delta0.1", p, got, "c128", 1e-9)
+
+
+def test_table54_setting_matches_oracle():
+    """Setting of Table 5.4 (d = 10, N = 32, s = 1000, unit moduli, SNR 30 dB noise, r = 2,
+    delta = 1e-12), complex128: the solve reproduces the oracle's stored solve exactly."""
+    require_gpu()
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = sweep_t54(0, 30.0)
+    got = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed), delta=1e-12, s=1000, r=2,
+                      b=10, seed=S0 + 54000, dtype="c128", cap=1000)
+    _compare_with_golden("t54_snr30_r2", p, got, "c128", 1e-9)
+
+
+# ---- exhausted Alg. 1 retries (reading R4), failing black box, streams, reproducibility --------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("seed", [5, 42])
+def test_uncovered_step_matches_oracle(seed, dtype):
+    """Alg. 3 step 2b with a single Alg. 1 call (b = 1) that does not reconstruct J_t (c = 4 and
+    gamma = 0.999 leave two to four lattices): the kept lattices, the per-step uncovered counts
+    and the output (the uncovered frequency has counter 0, so it is never detected) equal the
+    oracle's, and the library reports MR1L_WARN_UNCOVERED.  Seed 5 leaves a frequency uncovered at
+    step 2 and misses a planted one; seed 42 at the last step."""
+    require_gpu()
+    from paper_1711_05152_amd import _lib
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = random_planted(rng_for(404), 3, 4, 8, "unit")
+    delta = 1e-9 if dtype == "c128" else 1e-4     # above the rounding level of the transforms
+    got = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=delta, s=8, r=1, b=1, seed=seed,
+                      dtype=dtype, c=4.0, gamma=0.999, cap=8)
+    ref = oracle_sfft(p.lo, p.hi, PlantedBlackBox(p.freqs, p.coeffs), delta, 8, r=1, b=1, seed=seed, c=4.0,
+                      gamma=0.999)
+    assert sum(step["uncovered"] for step in ref.steps[1:]) > 0
+    assert got.status == _lib.MR1L_WARN_UNCOVERED
+    assert np.array_equal(got.freqs, ref.freqs)
+    assert got.freqs.shape[0] < 8 or seed != 5
+    for step in ref.steps[1:]:
+        t = step["t"]
+        for k in ("L", "sumM", "calls", "uncovered", "n_J"):
+            assert got.stats[k][t - 1] == step[k], (seed, t, k)
+    assert got.stats["samples"] == ref.samples
+    assert_close(got.coeffs, ref.coeffs, dtype, "coefficients after an uncovered step")
+
+
+def test_failing_sampler_reports_callback_error():
+    """A caller black box that fails (on the 1-D lines, or later on the lattice nodes) makes
+    sfft_detect return MR1L_ERR_CALLBACK; the library stays usable afterwards."""
+    torch = require_gpu()
+    from paper_1711_05152_amd import _lib
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = planted_c1()
+    hf = torch.tensor(p.freqs, dtype=torch.float64, device="cuda:0")
+    hc = torch.tensor(p.coeffs, dtype=torch.complex128, device="cuda:0")
+    K = int(p.hi[0] - p.lo[0] + 1)
+
+    def fails_always(x):
+        raise RuntimeError("black box failed")
+
+    def fails_on_lattices(x):
+        if x.shape[0] > K:
+            raise RuntimeError("black box failed on a lattice")
+        return torch.exp(2j * np.pi * ((x @ hf.T) % 1.0)) @ hc
+
+    for sampler in (fails_always, fails_on_lattices):
+        with pytest.raises(_lib.Mr1lError) as ei:
+            sfft_detect(p.lo, p.hi, sampler=sampler, delta=1e-12, s=50, r=1, b=10, seed=SEED1, dtype="c128")
+        assert ei.value.status == 5, ei.value
+    res = _run(p, "c128", 1e-12, 50, 1)
+    assert np.array_equal(res.freqs, p.freqs[_lex(p.freqs)])
+
+
+def test_callback_sampler_on_non_default_stream():
+    """The caller's black box runs on the library's stream (the one that wrote the nodes), also
+    when torch's current stream is another one: same result as the built-in black box."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.sfft import sfft_detect
+    p = random_planted(rng_for(406), 4, 6, 40, "unit")
+    hf = torch.tensor(p.freqs, dtype=torch.float64, device="cuda:0")
+    hc = torch.tensor(p.coeffs, dtype=torch.complex128, device="cuda:0")
+
+    def sampler(x):
+        return torch.exp(2j * np.pi * ((x @ hf.T) % 1.0)) @ hc
+
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        cb = sfft_detect(p.lo, p.hi, sampler=sampler, delta=1e-9, s=40, r=2, b=10, seed=12, dtype="c128")
+    torch.cuda.synchronize()
+    pl = _run(p, "c128", 1e-9, 40, 2, seed=12)
+    assert np.array_equal(cb.freqs, pl.freqs)
+    assert np.abs(cb.coeffs - pl.coeffs).max() < 1e-10
+    assert np.array_equal(cb.freqs, p.freqs[_lex(p.freqs)])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_solves_are_bit_reproducible(dtype):
+    """Two identical solves (built-in noisy black box, repetitions as right-hand sides) give
+    bit-identical coefficients and identical statistics: the synthesis of the samples sums every
+    bin in a fixed order."""
+    require_gpu()
+    p = random_planted(rng_for(405), 5, 8, 50, "unit", sigma=1e-3, noise_seed=3)
+    runs = [_run(p, dtype, 1e-2, 50, 2, seed=11) for _ in range(2)]
+    a, b = runs
+    assert np.array_equal(a.freqs, b.freqs)
+    assert np.array_equal(a.coeffs.view(np.float64), b.coeffs.view(np.float64))
+    for k in ("n_It", "n_J", "n_detected", "L", "sumM", "calls", "uncovered", "samples"):
+        assert a.stats[k] == b.stats[k], k
 
 
 # ---- construction variant with redraws, component order --------------------------------------------
