@@ -136,6 +136,18 @@ mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_unco
 mr1l_status mr1l_lsq_residual(mr1l_plan_t plan, const void* s, const void* y, const double* scale, void* grad,
                               double* loss, void* stream);
 
+/* Allocation-free mr1l_lsq_residual, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving or training loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as mr1l_lsq_residual (bit-identical), but the block partials of the loss live
+ * in one fixed device array per GPU (1 MiB, held until the process ends, looked up on the first call
+ * on each device) instead of a plan buffer: no call allocates or frees anything.  Limit: with a loss
+ * requested, 64 L n_rhs <= 131072 (else MR1L_ERR_UNSUPPORTED and nothing is launched).  Every call
+ * on one GPU uses that GPU's array: calls that overlap on one GPU (different streams or host
+ * threads without ordering between them) race and must not be issued.  Errors: MR1L_ERR_ARG as for
+ * mr1l_lsq_residual, MR1L_ERR_HIP when the array's address cannot be obtained. */
+mr1l_status mr1l_lsq_residual_noalloc(mr1l_plan_t plan, const void* s, const void* y, const double* scale,
+                                      void* grad, double* loss, void* stream);
+
 /* Plan-cached index work.  The residues r_l(k) and the alias bitmaps of Alg. 2 depend only on I
  * and the lattices, not on the samples or coefficients.  By default every forward and adjoint call
  * recomputes them (Alg. 2 as stated).  With enable = 1 the next call computes them once and later
