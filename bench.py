@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sparse-FFT, batched and gradient-descent workloads")
     ap.add_argument("--gd-steps", type=int, default=5)
+    ap.add_argument("--only", choices=["sfft", "batched", "batched_plan", "autograd", "throughput"],
+                    help="run only this extra workload and print its figures (for profiling it alone)")
     ap.add_argument("--sweeps", type=int, default=0, metavar="REPS",
                     help="also run the success-rate (Table 5.2 setting) and noise (Table 5.4 setting) "
                          "sweeps with REPS seeded instances per cell")
@@ -207,10 +209,23 @@ def _recovery(res, p):
     return correct, math.sqrt(err2) / float(np.linalg.norm(p.coeffs))
 
 
-def sweep_table52(reps: int, cells=None, dtype: str = "c128"):
+def solve_all(jobs, workers: int = 1):
+    """Run independent sparse-FFT solves: ``jobs`` is a list of zero-argument callables, each one
+    solve.  With workers > 1 they run on that many host threads, each solve on its own HIP stream
+    (sfft_detect creates one per call and releases the interpreter while it runs), so several
+    solves are in flight on the device at once.  Results keep the order of ``jobs``."""
+    if workers <= 1:
+        return [job() for job in jobs]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda job: job(), jobs))
+
+
+def sweep_table52(reps: int, cells=None, dtype: str = "c128", workers: int = 1):
     """Success rate and minimal number of correctly detected frequencies of Alg. 3 (setting of
     Table 5.2: d = 5, N = 32, s = 1000, unit-modulus coefficients) for each (r, delta) cell, over
-    ``reps`` seeded instances, beside the paper's values from 1000 repetitions."""
+    ``reps`` seeded instances (``workers`` solves in flight at once), beside the paper's values from
+    1000 repetitions."""
     from paper_1711_05152_amd.sfft import sfft_detect
     from workloads import S0, sweep_t52
     out = []
@@ -218,26 +233,34 @@ def sweep_table52(reps: int, cells=None, dtype: str = "c128"):
         r = int(r)
         if cells is not None and (r, delta) not in cells:
             continue
+        probs = [sweep_t52(rep) for rep in range(reps)]
+
+        def job(rep, r=r, delta=delta):
+            p = probs[rep]
+            return sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=delta, s=1000, r=r, b=10,
+                               seed=S0 + 52000 + rep, dtype=dtype, cap=1000)
+        t0 = time.perf_counter()
+        results = solve_all([lambda rep=rep: job(rep) for rep in range(reps)], workers)
+        secs = time.perf_counter() - t0
         ok, mins = 0, []
-        for rep in range(reps):
-            p = sweep_t52(rep)
-            res = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, 0.0, 0), delta=delta, s=1000, r=r, b=10,
-                              seed=S0 + 52000 + rep, dtype=dtype, cap=1000)
+        for p, res in zip(probs, results):
             correct, _ = _recovery(res, p)
             mins.append(correct)
             ok += correct == 1000
         out.append({"r": r, "delta": delta, "reps": reps, "success_rate": ok / max(1, reps),
                     "min_correct": min(mins) if mins else None, "paper_success_rate": prate,
-                    "paper_min_correct": int(pmin), "paper_reps": 1000})
+                    "paper_min_correct": int(pmin), "paper_reps": 1000, "workers": workers,
+                    "solves_per_s": reps / secs})
         print("sweep table 5.2 cell", json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
 
 
-def sweep_table54(reps: int, rows=None, dtype: str = "c128"):
+def sweep_table54(reps: int, rows=None, dtype: str = "c128", workers: int = 1):
     """Alg. 3 on noisy samples (setting of Table 5.4: d = 10, N = 32, s = 1000, delta = 1e-12,
-    sigma = sqrt(s / SNR)) for each (SNR dB, r) row over ``reps`` seeded instances: maximal sample
-    count, minimal number of correctly detected frequencies, success rate, maximal relative l2
-    error, beside the paper's values from 1000 repetitions."""
+    sigma = sqrt(s / SNR)) for each (SNR dB, r) row over ``reps`` seeded instances (``workers``
+    solves in flight at once): maximal sample count, minimal number of correctly detected
+    frequencies, success rate, maximal relative l2 error, beside the paper's values from 1000
+    repetitions."""
     from paper_1711_05152_amd.sfft import sfft_detect
     from workloads import S0, sweep_t54
     out = []
@@ -245,11 +268,17 @@ def sweep_table54(reps: int, rows=None, dtype: str = "c128"):
         r = int(r)
         if rows is not None and (int(snr), r) not in rows:
             continue
+        probs = [sweep_t54(rep, snr) for rep in range(reps)]
+
+        def job(rep, r=r):
+            p = probs[rep]
+            return sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed), delta=1e-12, s=1000,
+                               r=r, b=10, seed=S0 + 54000 + rep, dtype=dtype, cap=1000)
+        t0 = time.perf_counter()
+        results = solve_all([lambda rep=rep: job(rep) for rep in range(reps)], workers)
+        secs = time.perf_counter() - t0
         ok, mins, errs, samples = 0, [], [], []
-        for rep in range(reps):
-            p = sweep_t54(rep, snr)
-            res = sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed), delta=1e-12, s=1000,
-                              r=r, b=10, seed=S0 + 54000 + rep, dtype=dtype, cap=1000)
+        for p, res in zip(probs, results):
             correct, err = _recovery(res, p)
             mins.append(correct)
             errs.append(err)
@@ -259,7 +288,8 @@ def sweep_table54(reps: int, rows=None, dtype: str = "c128"):
                     "max_samples": max(samples) if samples else None, "min_correct": min(mins) if mins else None,
                     "success_rate": ok / max(1, reps), "max_rel_l2_error": max(errs) if errs else None,
                     "paper_max_samples": int(psamp), "paper_min_correct": int(pmin), "paper_success_rate": prate,
-                    "paper_max_rel_l2_error": perr, "paper_reps": 1000})
+                    "paper_max_rel_l2_error": perr, "paper_reps": 1000, "workers": workers,
+                    "solves_per_s": reps / secs})
         print("sweep table 5.4 row", json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
 
@@ -326,18 +356,26 @@ def sweep_table58(reps: int, rows=None, dtype: str = "c128", max_N: int = 1 << 3
     return out
 
 
-def extra_batched():
+def extra_batched(with_plain: bool = True):
     """512 independent transforms (d=15, |I_b| log-uniform in [2^8,2^18], L_b = ceil(log2 |I_b|),
-    primes in [|I_b|, 2|I_b|]): one batched plan (eager and HIP-graph replay) vs one plan per
-    transform launched one after another.  Forward + adjoint per step."""
+    primes in [|I_b|, 2|I_b|]), forward + adjoint per step, three ways: one batched plan whose small
+    transforms (one-block Bluestein lengths, at most 2048 frequencies) run whole in the persistent
+    in-block launch and the rest in the stage sweep (eager, and captured in a HIP graph); the same
+    plan with every transform in the stage sweep; one plan per transform, launched one after
+    another."""
     import numpy as np
     import torch
-    from paper_1711_05152_amd.mr1l import BatchedPlan, Plan
+    from paper_1711_05152_amd.mr1l import BatchedPlan, Plan, batch_inblock
     from workloads import batched_c4
     probs = batched_c4(with_data=False)
     ntot = sum(p.n for p in probs)
     g = torch.Generator(device="cuda:0").manual_seed(4)
     bp = BatchedPlan([(p.freqs, p.M, p.z) for p in probs], dtype="c64", device=0)
+    try:
+        batch_inblock(0)
+        bs = BatchedPlan([(p.freqs, p.M, p.z) for p in probs], dtype="c64", device=0)
+    finally:
+        batch_inblock(1)
     y = torch.randn(bp.sum_M, dtype=torch.complex64, device="cuda:0", generator=g)[None, :]
     c = torch.randn(bp.n, dtype=torch.complex64, device="cuda:0", generator=g)[None, :]
     co, yo = bp.empty_coeffs(), bp.empty_samples()
@@ -351,10 +389,20 @@ def extra_batched():
         _sync()
         return (time.perf_counter() - t0) * 1e3 / reps
 
+    t_sweep = timeit(lambda: (bs.forward(y, out=co), bs.adjoint(c, out=yo)))
     t_batched = timeit(lambda: (bp.forward(y, out=co), bp.adjoint(c, out=yo)))
     gf = bp.capture("forward", y, co)
     ga = bp.capture("adjoint", c, yo)
     t_graph = timeit(lambda: (gf.replay(), ga.replay()))
+    small = [b for b, p in enumerate(probs) if p.n <= 2048 and 2 * int(p.M.max()) - 1 <= 4096]
+    out = {"transforms": len(probs), "sum_n": int(ntot), "sum_M": int(bp.sum_M),
+           "inblock_transforms": len(small), "inblock_frequencies": int(sum(probs[b].n for b in small)),
+           "ms_fwd_adj_stage_sweep": t_sweep, "ms_fwd_adj_batched": t_batched,
+           "ms_fwd_adj_batched_graph": t_graph, "freqs_per_s_batched_graph": ntot / (t_graph * 1e-3),
+           "stage_sweep_over_inblock": t_sweep / t_batched}
+    del bs
+    if not with_plain:
+        return out
     plans = [Plan(p.freqs, p.M, p.z, dtype="c64", device=0) for p in probs]
     fo = np.concatenate([[0], np.cumsum([p.n for p in probs])])
     so = np.concatenate([[0], np.cumsum([int(p.M.sum()) for p in probs])])
@@ -370,10 +418,34 @@ def extra_batched():
             pl.forward(ys[b], out=cos[b])
             pl.adjoint(cs[b], out=yos[b])
     t_plain = timeit(plain, reps=3)
-    return {"transforms": len(probs), "sum_n": int(ntot), "sum_M": int(bp.sum_M),
-            "ms_fwd_adj_batched": t_batched, "ms_fwd_adj_batched_graph": t_graph, "ms_fwd_adj_plain": t_plain,
-            "freqs_per_s_batched_graph": ntot / (t_graph * 1e-3), "freqs_per_s_plain": ntot / (t_plain * 1e-3),
-            "plain_over_batched_graph": t_plain / t_graph}
+    out.update({"ms_fwd_adj_plain": t_plain, "freqs_per_s_plain": ntot / (t_plain * 1e-3),
+                "plain_over_batched_graph": t_plain / t_graph})
+    return out
+
+
+def extra_sweep_throughput(reps: int = 16, workers: int = 8):
+    """Independent solves of one sweep cell (Table 5.2 setting, r = 2, delta = 0.1, complex128):
+    solves per second one after another and with ``workers`` solves in flight; the two runs give
+    bit-identical results."""
+    import numpy as np
+    from paper_1711_05152_amd.sfft import sfft_detect
+    from workloads import S0, sweep_t52
+    probs = [sweep_t52(rep) for rep in range(reps)]
+    jobs = [lambda rep=rep: sfft_detect(probs[rep].lo, probs[rep].hi,
+                                        planted=(probs[rep].freqs, probs[rep].coeffs, 0.0, 0), delta=0.1, s=1000,
+                                        r=2, b=10, seed=S0 + 52000 + rep, dtype="c128", cap=1000)
+            for rep in range(reps)]
+    solve_all(jobs[:2], 1)   # warm-up
+    out = {"cell": "d=5 N=32 s=1000 r=2 delta=0.1 complex128", "solves": reps}
+    res = {}
+    for w in (1, workers):
+        t0 = time.perf_counter()
+        res[w] = solve_all(jobs, w)
+        out[f"solves_per_s_{w}_in_flight"] = reps / (time.perf_counter() - t0)
+    out["identical"] = all(np.array_equal(a.freqs, b.freqs) and np.array_equal(a.coeffs, b.coeffs)
+                           for a, b in zip(res[1], res[workers]))
+    out["concurrent_over_serial"] = out[f"solves_per_s_{workers}_in_flight"] / out["solves_per_s_1_in_flight"]
+    return out
 
 
 def extra_autograd(steps: int):
@@ -766,6 +838,12 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only:
+        fn = {"sfft": extra_sfft, "batched": extra_batched, "batched_plan": lambda: extra_batched(False),
+              "autograd": lambda: extra_autograd(args.gd_steps),
+              "throughput": extra_sweep_throughput}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     p = standalone_c2()
     n, d, L = p.n, p.d, len(p.M)
     sumM = int(p.M.sum())
@@ -874,6 +952,8 @@ def main():
         _progress("batched transforms timed")
         extra["autograd_lsq"] = extra_autograd(args.gd_steps)
         _progress("gradient-descent steps timed")
+        extra["sweep_throughput"] = extra_sweep_throughput()
+        _progress("independent solves timed")
         line["extra"] = extra
     if args.sweeps > 0:
         t0 = time.perf_counter()

@@ -173,6 +173,16 @@ mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current);
  * receives the bound in effect.  Never fails. */
 mr1l_status mr1l_work_limit(int64_t max_bytes, int64_t* current);
 
+/* Persistent in-block kernel of batched plans.  With enable = 1 (the default), a batched plan with
+ * the weights of Alg. 2 and one right-hand side runs every transform whose lattices all have a
+ * Bluestein length of at most 2^12 and that has at most 2048 frequencies in one persistent launch:
+ * each workgroup takes a whole transform (residues, alias counts, prime-length DFTs, average or
+ * scatter) from a work queue until none is left; the other transforms take the stage sweep.
+ * Results are the same bits either way.  enable = 0 sends every transform to the stage sweep,
+ * < 0 only queries; ``current`` (optional) receives the setting.  Plans read it when they are
+ * created.  Never fails. */
+mr1l_status mr1l_batch_inblock(int enable, int* current);
+
 /* Device-memory cache.  Every device buffer of the library (plan work areas, sparse-FFT steps)
  * comes from a per-device cache of size-classed blocks: a released block stays mapped and serves
  * later requests of its class, because allocating and freeing multi-GB regions through the driver

@@ -61,6 +61,8 @@ struct TxDesc {
     int64_t fn;
     int32_t lat0;
     int32_t nlat;
+    int32_t in_block;  // 1: the persistent small-transform kernel does this transform's forward and
+    int32_t pad_;      //    adjoint in one workgroup; the FFT stages, the gather and the scatter skip it
 };
 
 // One workgroup of the alias-histogram pass: lattice l, bins [m0, m1) (multiples of 32 except
@@ -222,6 +224,18 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
 template <typename T>
 void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int64_t dst_stride, bool dst_is_samples,
                int sign, bool scale_by_invM, hipStream_t s);
+
+// Persistent small-transform kernel of batched plans (Alg. 2 and its adjoint, weights of Alg. 2):
+// one workgroup takes a whole transform from a work queue (list[0 .. nlist), transforms whose
+// lattices all have one-block Bluestein lengths and at most kFusedTxMaxN frequencies), computes
+// residues and alias bitmaps in LDS, runs each lattice's prime-length DFT in LDS and averages
+// (forward) or scatters and transforms back (adjoint), and takes the next transform until the queue
+// is empty.  queue: two device ints, zero before the launch and zero again after it (the last
+// workgroup to finish resets them), so a captured graph can replay the launch.
+constexpr int kFusedTxMaxN = 2048;
+template <typename T>
+void launch_fused_small(const TxArgs& a, const int* list, int nlist, int* queue, const cx<T>* src, cx<T>* dst,
+                        const cx<T>* filt, bool forward, hipStream_t s);
 
 // Filter spectra: filt_l = DFT_{2^lgN}(b_l) / 2^lgN with b_l[n] = e^{+i pi n^2 / M_l} for |n| < M_l
 // (wrapped), stored in the layout stage 2 reads (natural order on the one-block path,

@@ -23,6 +23,7 @@ struct InitOverrides {
 
 constexpr int64_t kDefaultWorkLimit = (int64_t)4 << 30;
 std::atomic<int64_t> g_work_limit{kDefaultWorkLimit};
+std::atomic<int> g_inblock{1};
 
 int table_split(int dt, int lgN) {
     const int t = kTunedSplit[dt][lgN];
@@ -38,6 +39,7 @@ int fft_split(int dtype, int lgN) {
 }
 
 int64_t work_limit_bytes() { return g_work_limit.load(); }
+bool batch_inblock_enabled() { return g_inblock.load() != 0; }
 
 }  // namespace mr1l
 
@@ -48,6 +50,13 @@ extern "C" mr1l_status mr1l_work_limit(int64_t max_bytes, int64_t* current) {
     if (max_bytes > 0) g_work_limit.store(max_bytes);
     else if (max_bytes < 0) g_work_limit.store(kDefaultWorkLimit);
     if (current) *current = g_work_limit.load();
+    return MR1L_OK;
+}
+
+extern "C" mr1l_status mr1l_batch_inblock(int enable, int* current) {
+    clear_error();
+    if (enable >= 0) g_inblock.store(enable ? 1 : 0);
+    if (current) *current = g_inblock.load();
     return MR1L_OK;
 }
 

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.h"
+#include "index_dev.h"
 #include "runtime.h"
 
 namespace mr1l {
@@ -780,6 +781,14 @@ __global__ void k_filter_store(const LatDesc* __restrict__ desc, const cx<double
 }
 
 // ---- dispatch over compile-time sizes --------------------------------------------------------------
+template <int LO, int HI, typename F>
+__device__ __forceinline__ void with_lg_dev(int lg, F&& f) {
+    if constexpr (LO <= HI) {
+        if (lg == LO) f(std::integral_constant<int, LO>{});
+        else with_lg_dev<LO + 1, HI>(lg, f);
+    }
+}
+
 // f(std::integral_constant<int, lg>) for lg in [LO, HI]
 template <int LO, int HI, typename F>
 static void with_lg(int lg, F&& f) {
@@ -895,6 +904,191 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
                                hipStream_t);
 MR1L_INST_FFT(float)
 MR1L_INST_FFT(double)
+
+// ---- persistent small-transform kernel (batched plans) ---------------------------------------------
+// LDS of one workgroup: the Bluestein buffer (one-block path, up to 2^kSmallMaxLg points), the
+// single-precision phase table, per frequency its residue in the current lattice, its running sum
+// and its counter, and the alias bitmaps of the current lattice (at most 2^(kSmallMaxLg-1) bins).
+template <typename T>
+struct FusedLds {
+    static constexpr int kBuf = Padded<(1 << kSmallMaxLg)>::v;
+    static constexpr int kWords = (1 << (kSmallMaxLg - 1)) / 32;
+    cx<T> buf[kBuf];
+    cx<T> ph[PhaseTab<T>::n];
+    cx<T> acc[kFusedTxMaxN];
+    int32_t res[kFusedTxMaxN];
+    uint8_t cnt[kFusedTxMaxN];
+    uint32_t seen[kWords], multi[kWords];
+    int next;
+};
+
+// residues of the transform's frequencies in lattice D into L.res and the lattice's 2-bit alias
+// counts into L.seen / L.multi (same integers as the index pass); ends with a barrier
+template <typename T, typename K>
+__device__ void fused_alias(const TxArgs& a, const TxDesc& t, const LatDesc& D, FusedLds<T>& L) {
+    const int words = (int)D.bm_words;
+    for (int w = threadIdx.x; w < words; w += kThreads) {
+        L.seen[w] = 0u;
+        L.multi[w] = 0u;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < (int)t.fn; k += kThreads) {
+        const int r = (int)residue<K>(a, D, t.foff + k);
+        L.res[k] = r;
+        const uint32_t old = atomicOr(&L.seen[r >> 5], 1u << (r & 31));
+        if ((old >> (r & 31)) & 1u) atomicOr(&L.multi[r >> 5], 1u << (r & 31));
+    }
+    __syncthreads();
+}
+
+// the one-block Bluestein of k_small on L.buf, which holds the chirped, zero-padded input:
+// forward DFT, filter, inverse DFT; ends with a barrier
+template <typename T, int LGN>
+__device__ void fused_conv(cx<T>* buf, const cx<T>* __restrict__ f, int sign, const cx<T>* __restrict__ tw) {
+    constexpr int N = 1 << LGN;
+    fft_ct<T, LGN, 1, N, -1>(buf, tw);
+    for (int n = threadIdx.x; n < N; n += kThreads)
+        buf[pidx(n)] = sign < 0 ? cmul(buf[pidx(n)], f[n]) : cmulc(buf[pidx(n)], f[n]);
+    __syncthreads();
+    fft_ct<T, LGN, 1, N, +1>(buf, tw);
+}
+
+template <typename T>
+__device__ void fused_conv_any(int lgN, cx<T>* buf, const cx<T>* __restrict__ f, int sign,
+                               const cx<T>* __restrict__ tw) {
+    with_lg_dev<0, kSmallMaxLg>(lgN, [&](auto LG) { fused_conv<T, decltype(LG)::value>(buf, f, sign, tw); });
+}
+
+// FORWARD: c_k = (1/counter_k) sum over ascending l with k in I_l of DFT(y_l)[r_l(k)] / M_l.
+// Adjoint: y_l = (1/M_l) IDFT(bins_l), bins_l[r_l(k)] = c_k / counter_k for k in I_l.  Every
+// floating-point operation is the one the stage sweep does for the same transform (k_small, then
+// the gather's ascending sum and division, or the scatter's division, then k_small), so the two
+// paths give the same bits.
+template <typename T, typename K, bool FORWARD>
+__global__ __launch_bounds__(kThreads) void k_fused_small(TxArgs a, const int* __restrict__ list, int nlist,
+                                                         int* queue, const cx<T>* __restrict__ src, cx<T>* dst,
+                                                         const cx<T>* __restrict__ filt,
+                                                         const cx<T>* __restrict__ tw) {
+    extern __shared__ __align__(16) char fused_raw[];
+    FusedLds<T>& L = *reinterpret_cast<FusedLds<T>*>(fused_raw);
+    phase_fill<T>(L.ph);
+    for (;;) {
+        if (threadIdx.x == 0) L.next = atomicAdd(&queue[0], 1);
+        __syncthreads();
+        const int b = L.next;
+        __syncthreads();
+        if (b >= nlist) break;
+        const TxDesc t = a.tx[list[b]];
+        const int fn = (int)t.fn;
+        for (int k = threadIdx.x; k < fn; k += kThreads) {
+            L.acc[k] = {(T)0, (T)0};
+            L.cnt[k] = 0;
+        }
+        if (!FORWARD) {
+            // counter_k over every lattice first
+            for (int j = 0; j < t.nlat; ++j) {
+                const LatDesc D = a.desc[t.lat0 + j];
+                fused_alias<T, K>(a, t, D, L);
+                for (int k = threadIdx.x; k < fn; k += kThreads) {
+                    const int r = L.res[k];
+                    if (!((L.multi[r >> 5] >> (r & 31)) & 1u)) ++L.cnt[k];
+                }
+                __syncthreads();
+            }
+        }
+        for (int j = 0; j < t.nlat; ++j) {
+            const LatDesc D = a.desc[t.lat0 + j];
+            const int N = 1 << D.lgN;
+            fused_alias<T, K>(a, t, D, L);
+            if (FORWARD) {
+                const cx<T>* in = src + D.samp_off;
+                for (int n = threadIdx.x; n < N; n += kThreads) {
+                    cx<T> v = {(T)0, (T)0};
+                    if (n < D.M) v = cmul(in[n], chirp<T>(n, D.M, D.invM, -1, L.ph));
+                    L.buf[pidx(n)] = v;
+                }
+            } else {
+                for (int n = threadIdx.x; n < N; n += kThreads) L.buf[pidx(n)] = {(T)0, (T)0};
+                __syncthreads();
+                // bins of the frequencies in I_l: c_k / counter_k
+                for (int k = threadIdx.x; k < fn; k += kThreads) {
+                    const int r = L.res[k];
+                    if (!((L.multi[r >> 5] >> (r & 31)) & 1u)) {
+                        const cx<T> c = src[t.foff + k];
+                        L.buf[pidx(r)] = {c.x / (T)L.cnt[k], c.y / (T)L.cnt[k]};
+                    }
+                }
+                __syncthreads();
+                for (int n = threadIdx.x; n < D.M; n += kThreads) {
+                    const bool own = ((L.seen[n >> 5] & ~L.multi[n >> 5]) >> (n & 31)) & 1u;
+                    L.buf[pidx(n)] = own ? cmul(L.buf[pidx(n)], chirp<T>(n, D.M, D.invM, +1, L.ph)) : cx<T>{(T)0, (T)0};
+                }
+            }
+            __syncthreads();
+            fused_conv_any<T>(D.lgN, L.buf, filt + D.filt_off, FORWARD ? -1 : +1, tw);
+            if (FORWARD) {
+                // DFT bins (chirp, 1/M) in place, then the ascending-l sum of the frequencies in I_l
+                for (int n = threadIdx.x; n < D.M; n += kThreads)
+                    L.buf[pidx(n)] = cscale(cmul(L.buf[pidx(n)], chirp<T>(n, D.M, D.invM, -1, L.ph)), (T)D.invM);
+                __syncthreads();
+                for (int k = threadIdx.x; k < fn; k += kThreads) {
+                    const int r = L.res[k];
+                    if (!((L.multi[r >> 5] >> (r & 31)) & 1u)) {
+                        L.acc[k] = L.acc[k] + L.buf[pidx(r)];
+                        ++L.cnt[k];
+                    }
+                }
+            } else {
+                cx<T>* out = dst + D.samp_off;
+                for (int n = threadIdx.x; n < D.M; n += kThreads)
+                    out[n] = cscale(cmul(L.buf[pidx(n)], chirp<T>(n, D.M, D.invM, +1, L.ph)), (T)D.invM);
+            }
+            __syncthreads();
+        }
+        if (FORWARD)
+            for (int k = threadIdx.x; k < fn; k += kThreads) {
+                const int c = L.cnt[k];
+                dst[t.foff + k] = c ? cx<T>{L.acc[k].x / (T)c, L.acc[k].y / (T)c} : cx<T>{(T)0, (T)0};
+            }
+        __syncthreads();
+    }
+    // the last workgroup out empties the queue for the next launch: every workgroup's last fetch
+    // returned before it counted itself done
+    if (threadIdx.x == 0 && atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+        atomicExch(&queue[0], 0);
+        atomicExch(&queue[1], 0);
+    }
+}
+
+template <typename T>
+void launch_fused_small(const TxArgs& a, const int* list, int nlist, int* queue, const cx<T>* src, cx<T>* dst,
+                        const cx<T>* filt, bool forward, hipStream_t s) {
+    if (nlist == 0) return;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const cx<T>* tw = twiddles<T>(dev);
+    const size_t lds = sizeof(FusedLds<T>);
+    const int per_cu = std::max(1, (int)((160u * 1024u) / lds));
+    const dim3 grid((unsigned)std::min(nlist, 256 * per_cu));
+    auto go = [&](auto Kc) {
+        using K = decltype(Kc);
+        if (forward)
+            hipLaunchKernelGGL((k_fused_small<T, K, true>), grid, dim3(kThreads), lds, s, a, list, nlist, queue, src,
+                               dst, filt, tw);
+        else
+            hipLaunchKernelGGL((k_fused_small<T, K, false>), grid, dim3(kThreads), lds, s, a, list, nlist, queue, src,
+                               dst, filt, tw);
+    };
+    switch (a.fv.ktype) {
+        case K_I8: go(int8_t{}); break;
+        case K_I16: go(int16_t{}); break;
+        default: go(int32_t{}); break;
+    }
+}
+template void launch_fused_small<float>(const TxArgs&, const int*, int, int*, const cx<float>*, cx<float>*,
+                                        const cx<float>*, bool, hipStream_t);
+template void launch_fused_small<double>(const TxArgs&, const int*, int, int*, const cx<double>*, cx<double>*,
+                                         const cx<double>*, bool, hipStream_t);
 
 // Filter spectra for every lattice of a plan (synchronous on s).  The double-precision DFT of
 // b_l reuses the stage-1/stage-2 kernels (or the one-block DFT) on a temporary buffer laid out

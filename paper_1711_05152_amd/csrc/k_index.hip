@@ -27,7 +27,7 @@ __global__ void k_clear_u32(uint32_t* p, int64_t words) {
 // bounds and descriptor addresses are uniform across the wavefront (scalar loads).
 template <bool SINGLE>
 __device__ __forceinline__ TxDesc get_tx(const TxArgs& a, int64_t g) {
-    if (SINGLE) return TxDesc{0, a.n, 0, a.L};
+    if (SINGLE) return TxDesc{0, a.n, 0, a.L, 0, 0};
     return a.tx[find_tx(a.tx_foff, a.ntx + 1, g)];
 }
 
@@ -300,6 +300,7 @@ __global__ __launch_bounds__(256) void k_gather(TxArgs a, const cx<T>* __restric
     const int nr = (int)min((int64_t)RB, a.n_rhs - rhs0);
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
         const TxDesc t = get_tx<SINGLE>(a, g);
+        if (t.in_block) continue;   // the persistent small-transform kernel writes these
         cx<T> acc[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) acc[q] = {(T)0, (T)0};
@@ -356,7 +357,7 @@ constexpr int kSplitSlots = 2;   // slots per lane per pass (16 lattice slots of
 // transforms)
 template <bool SINGLE>
 __device__ __forceinline__ TxDesc split_tx(const TxArgs& a, int64_t g, int sub, int lead) {
-    if (SINGLE) return TxDesc{0, a.n, 0, a.L};
+    if (SINGLE) return TxDesc{0, a.n, 0, a.L, 0, 0};
     int ti = 0;
     if (sub == 0) ti = find_tx(a.tx_foff, a.ntx + 1, g);
     ti = __shfl(ti, lead);
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256) void k_gather_split(TxArgs a, const cx<T>* __r
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / kSplit;
     for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSplit; g < a.n; g += stride) {
         const TxDesc t = split_tx<SINGLE>(a, g, sub, lead);
+        if (t.in_block) continue;   // the persistent small-transform kernel writes these
         cx<T> acc = {(T)0, (T)0};
         int cnt = 0;
         for (int j0 = 0; j0 < t.nlat; j0 += kSplit * kSplitSlots) {
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(256) void k_scatter_split(TxArgs a, const cx<T>* __
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / kSplit;
     for (int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSplit; g < a.n; g += stride) {
         const TxDesc t = split_tx<SINGLE>(a, g, sub, lead);
-        if (t.nlat == 0) continue;
+        if (t.nlat == 0 || t.in_block) continue;
         const cx<T> c = coeffs[g];
         // counter_k over all slots (the first pass's slots are kept for the writes)
         int32_t r[kSplitSlots];
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(256) void k_scatter(TxArgs a, const cx<T>* __restri
         cx<T> v[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) v[q] = (q < nr) ? coeffs[(rhs0 + q) * a.n + g] : cx<T>{(T)0, (T)0};
-        if (t.nlat == 0) continue;
+        if (t.nlat == 0 || t.in_block) continue;
         int32_t r[LC];
         uint32_t use = unaliased_chunk<LC>(a, t, 0, g, r);
         int cnt = __popc(use);

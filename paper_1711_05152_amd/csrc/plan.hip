@@ -18,9 +18,15 @@ void set_error(const std::string& msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
 static const char* kStageNames[MR1L_NSTAGES] = {"alias_hist", "bluestein_small", "bluestein_p1", "bluestein_p2",
-                                                "bluestein_p3", "gather",        "scatter",      "unused"};
+                                                "bluestein_p3", "gather",        "scatter",      "inblock_small"};
 
 Plan::~Plan() {
+    if (side) {
+        (void)hipStreamSynchronize(side);
+        (void)hipStreamDestroy(side);
+    }
+    if (fork) hipEventDestroy(fork);
+    if (join) hipEventDestroy(join);
     for (auto& r : pending) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -286,6 +292,34 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
 
     for (int i = 0; i < ntx; ++i)
         for (int l = P->htx[i].lat0; l < P->htx[i].lat0 + P->htx[i].nlat; ++l) P->hdesc[l].tx = i;
+    // transforms of a batched plan (Alg. 2 weights, one right-hand side) whose lattices all take
+    // the one-block Bluestein path and whose frequencies fit one workgroup's LDS run whole in the
+    // persistent in-block kernel, largest first so that the queue drains evenly
+    std::vector<int> inblock;
+    if (ntx > 1 && sp.weights == MR1L_W_PAPER && sp.n_rhs == 1 && batch_inblock_enabled()) {
+        for (int i = 0; i < ntx; ++i) {
+            TxDesc& t = P->htx[i];
+            bool ok = t.nlat >= 1 && t.fn >= 1 && t.fn <= kFusedTxMaxN;
+            for (int l = t.lat0; ok && l < t.lat0 + t.nlat; ++l) ok = P->hdesc[l].small;
+            if (ok) {
+                t.in_block = 1;
+                inblock.push_back(i);
+            }
+        }
+        std::stable_sort(inblock.begin(), inblock.end(), [&](int x, int y) {
+            return P->htx[x].fn * P->htx[x].nlat > P->htx[y].fn * P->htx[y].nlat;
+        });
+    }
+    P->n_inblock = (int)inblock.size();
+    if (P->n_inblock > 0) {
+        MR1L_HIP_TRY(stg.add(P->inblock, inblock.data(), inblock.size() * sizeof(int)));
+        const int zero[2] = {0, 0};
+        MR1L_HIP_TRY(stg.add(P->queue, zero, sizeof(zero)));
+        // default priority, like every stream of the library
+        MR1L_HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+        MR1L_HIP_TRY(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
+        MR1L_HIP_TRY(hipEventCreateWithFlags(&P->join, hipEventDisableTiming));
+    }
     MR1L_HIP_TRY(stg.add(P->tx, P->htx.data(), P->htx.size() * sizeof(TxDesc)));
     MR1L_HIP_TRY(stg.add(P->tx_foff, foff.data(), foff.size() * sizeof(int64_t)));
     MR1L_HIP_TRY(stg.add(P->z, zred.data(), zred.size() * sizeof(int64_t)));
@@ -305,6 +339,26 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             g.nlat = (int)by_len[g.lgN].size();
             g.lat = P->grp_lat.as<int>() + spans[i].second;
             P->groups.push_back(g);
+        }
+        // execution groups: the lattices of in-block transforms are done by the persistent kernel
+        if (P->n_inblock == 0) {
+            P->sweep = P->groups;
+        } else {
+            std::vector<int> sids;
+            std::vector<std::pair<const FftGroup*, std::pair<int, int>>> sspans;
+            for (size_t i = 0; i < spans.size(); ++i) {
+                const int first = (int)sids.size();
+                for (int l : by_len[spans[i].first])
+                    if (!P->htx[P->hdesc[l].tx].in_block) sids.push_back(l);
+                if ((int)sids.size() > first) sspans.push_back({&P->groups[i], {first, (int)sids.size() - first}});
+            }
+            if (!sids.empty()) MR1L_HIP_TRY(stg.add(P->sweep_lat, sids.data(), sids.size() * sizeof(int)));
+            for (auto& sg : sspans) {
+                FftGroup g = *sg.first;
+                g.nlat = sg.second.second;
+                g.lat = P->sweep_lat.as<int>() + sg.second.first;
+                P->sweep.push_back(g);
+            }
         }
     }
     // alias-histogram tiles: every lattice's bins split into ranges of <= 2^18 bins (multiples of
@@ -503,19 +557,41 @@ static void index_pass(Plan* p, bool eval, StageTimer& tm, hipStream_t s) {
     p->alias_valid = p->cache_alias;
 }
 
+// Fork the in-block launch onto the plan's side stream after the work already queued on s (the
+// caller joins with p->join before returning).  With stage timing on, the launch is timed on the
+// side stream.
+template <typename T>
+static hipError_t inblock_begin(Plan* p, const cx<T>* src, cx<T>* dst, bool forward, hipStream_t s) {
+    if (p->n_inblock == 0) return hipSuccess;
+    hipError_t e = hipEventRecord(p->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+    if (e != hipSuccess) return e;
+    StageTimer tm(p, p->side);
+    tm.begin(7);
+    launch_fused_small<T>(p->args, p->inblock.as<int>(), p->n_inblock, p->queue.as<int>(), src, dst,
+                          (const cx<T>*)p->filt_ptr, forward, p->side);
+    tm.end();
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
+    return e;
+}
+
 template <typename T>
 static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
+    // small transforms of a batch, whole, in one persistent launch on the side stream, beside the
+    // stage sweep of the others (they share no data)
+    MR1L_HIP_TRY(inblock_begin<T>(p, y, c, true, s));
     index_pass(p, eval, tm, s);
     for (int64_t r0 = 0; r0 < p->n_rhs; r0 += p->rhs_chunk) {
         TxArgs a = p->args;
         a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
         const cx<T>* yc = y + r0 * a.samp_stride;
         cx<T>* cc = c + r0 * a.n;
-        for (const FftGroup& g : p->groups) {
+        for (const FftGroup& g : p->sweep) {
             if (g.small) {
                 tm.begin(1);
                 launch_bluestein_small<T>(a, g, yc, a.samp_stride, true, work, filt, work, a.work_stride, false, -1,
@@ -537,6 +613,7 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
         launch_gather<T>(a, work, cc, eval, s);
         tm.end();
     }
+    if (p->n_inblock > 0) MR1L_HIP_TRY(hipStreamWaitEvent(s, p->join, 0));
     MR1L_HIP_TRY(hipGetLastError());
     return MR1L_OK;
 }
@@ -547,6 +624,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
+    MR1L_HIP_TRY(inblock_begin<T>(p, c, y, false, s));
     index_pass(p, eval, tm, s);
     if (eval && p->args.bsort && !(p->cache_alias && p->sort_valid)) {
         tm.begin(0);
@@ -567,7 +645,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
             launch_scatter<T>(a, cc, work, eval, s);
         }
         tm.end();
-        for (const FftGroup& g : p->groups) {
+        for (const FftGroup& g : p->sweep) {
             if (g.small) {
                 tm.begin(1);
                 launch_bluestein_small<T>(a, g, work, a.work_stride, false, work, filt, yc, a.samp_stride, true, +1,
@@ -586,6 +664,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
             tm.end();
         }
     }
+    if (p->n_inblock > 0) MR1L_HIP_TRY(hipStreamWaitEvent(s, p->join, 0));
     MR1L_HIP_TRY(hipGetLastError());
     return MR1L_OK;
 }

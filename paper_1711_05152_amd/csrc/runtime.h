@@ -116,6 +116,9 @@ using host::Rng;
 
 // Bound of a plan's Bluestein work area in bytes (process-wide, mr1l_work_limit; default 4 GiB).
 int64_t work_limit_bytes();
+// Whether batched plans run their small transforms in the persistent in-block kernel
+// (process-wide, mr1l_batch_inblock; default on).
+bool batch_inblock_enabled();
 
 // Description of the transforms a plan holds.  A plain plan has one transform; a batched plan
 // stacks several independent ones (own frequencies, own lattices).
@@ -159,7 +162,13 @@ struct Plan {
     int64_t bm_total = 0;
     DevMem freqs, desc, tx, tx_foff, z, z32, bitmaps, filt, work, grp_lat, res32, hist, rtiles, part, bcnt, bloc, bbase, perm;
     DevMem lsq_part;                   // block partials of mr1l_lsq_residual (allocated on first use)
-    std::vector<FftGroup> groups;   // lattices grouped by Bluestein length
+    std::vector<FftGroup> groups;   // lattices grouped by Bluestein length (filter construction)
+    std::vector<FftGroup> sweep;    // the same without the lattices of in-block transforms
+    DevMem sweep_lat;                  // lattice lists of the sweep groups
+    DevMem inblock, queue;             // in-block transforms (largest first) and their work queue
+    int n_inblock = 0;
+    hipStream_t side = nullptr;        // the in-block launch runs here, beside the stage sweep
+    hipEvent_t fork = nullptr, join = nullptr;
     void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};
     // plan-cached index work: residues and bitmaps valid from an earlier call

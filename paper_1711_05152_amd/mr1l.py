@@ -13,7 +13,8 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "memory_cache", "work_limit", "version"]
+__all__ = ["Plan", "BatchedPlan", "mr1l_plan", "mr1l_construct", "memory_cache", "work_limit", "batch_inblock",
+           "version"]
 
 _DT = {"c64": (_lib.C64, torch.complex64), "c128": (_lib.C128, torch.complex128)}
 _W = {"paper": _lib.W_PAPER, "eval": _lib.W_EVAL}
@@ -44,6 +45,14 @@ def work_limit(max_bytes: int = 0) -> int:
     < 0 restores the default, 0 queries); returns the bound in effect."""
     out = C.c_int64(0)
     check(lib().mr1l_work_limit(int(max_bytes), C.byref(out)), "mr1l_work_limit")
+    return int(out.value)
+
+
+def batch_inblock(enable: int = -1) -> int:
+    """mr1l_batch_inblock: whether batched plans created from now on run their small transforms in
+    the persistent in-block kernel (1 on, 0 off, < 0 query); returns the setting."""
+    out = C.c_int(0)
+    check(lib().mr1l_batch_inblock(int(enable), C.byref(out)), "mr1l_batch_inblock")
     return int(out.value)
 
 

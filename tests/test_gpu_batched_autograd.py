@@ -44,7 +44,36 @@ def test_batched_matches_oracle_and_plain(dtype):
         # the plain per-transform plan runs the same arithmetic
         pp = Plan(p.freqs, p.M, p.z, dtype=dtype, device=0)
         cp = pp.forward(_t(torch, p.samples, dtype)).cpu().numpy()[0]
+        yp = pp.adjoint(_t(torch, p.coeffs, dtype)).cpu().numpy()[0]
         assert np.array_equal(cp, cb[f0:f1])
+        assert np.array_equal(yp, yb[so[b]:so[b + 1]])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batched_inblock_kernel_matches_stage_sweep(dtype):
+    """The persistent in-block kernel (small transforms whole in one workgroup, from a work queue)
+    gives the bits of the stage sweep, in both directions, on a batch that mixes in-block and swept
+    transforms; two calls in a row (the queue is reset by the launch itself)."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import BatchedPlan, batch_inblock
+    probs = batched_c4(count=40, seed_extra=2, log2_lo=6.0, log2_hi=13.5)
+    y = _t(torch, np.concatenate([p.samples[0] for p in probs])[None, :], dtype)
+    c = _t(torch, np.concatenate([p.coeffs[0] for p in probs])[None, :], dtype)
+    assert batch_inblock() == 1
+    try:
+        batch_inblock(0)
+        swept = BatchedPlan([(p.freqs, p.M, p.z) for p in probs], dtype=dtype, device=0)
+    finally:
+        batch_inblock(1)
+    mixed = BatchedPlan([(p.freqs, p.M, p.z) for p in probs], dtype=dtype, device=0)
+    ref = (swept.forward(y), swept.adjoint(c))
+    n_small = sum(1 for p in probs if p.n <= 2048 and (2 * p.M.max() - 1) <= 4096)
+    print(f"{n_small} of {len(probs)} transforms in-block", flush=True)
+    assert 0 < n_small < len(probs)
+    for _ in range(2):
+        got = (mixed.forward(y), mixed.adjoint(c))
+        for a, b in zip(got, ref):
+            assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
 
 
 def test_batched_graph_replay():

@@ -411,3 +411,23 @@ def test_repeated_solves_reuse_staging_safely():
         if first is None:
             first = res.freqs
         assert np.array_equal(res.freqs, first), i
+
+
+def test_concurrent_solves_match_serial():
+    """Independent solves on several host threads (each sfft_detect on its own stream, several
+    in flight on the device) give bit-identical results to the same solves one after another."""
+    require_gpu()
+    import bench
+    from paper_1711_05152_amd.sfft import sfft_detect
+    probs = [random_planted(rng_for(407, i), 5, 16, 300, "unit", sigma=1e-3 * (i % 2), noise_seed=i)
+             for i in range(8)]
+    jobs = [lambda p=p, i=i: sfft_detect(p.lo, p.hi, planted=(p.freqs, p.coeffs, p.sigma, p.noise_seed),
+                                         delta=1e-2, s=300, r=2, b=10, seed=100 + i,
+                                         dtype="c64" if i % 3 == 0 else "c128", cap=300)
+            for i, p in enumerate(probs)]
+    serial = bench.solve_all(jobs, 1)
+    concurrent = bench.solve_all(jobs, 4)
+    for i, (a, b) in enumerate(zip(serial, concurrent)):
+        assert np.array_equal(a.freqs, b.freqs), i
+        assert np.array_equal(a.coeffs.view(np.float64), b.coeffs.view(np.float64)), i
+        assert a.stats["samples"] == b.stats["samples"], i
