@@ -14,9 +14,12 @@
 namespace mr1l {
 namespace {
 std::atomic<int> g_override[2][kMaxLgN + 1];
+std::atomic<int> g_p2_override[2][kMaxLgN + 1];
 struct InitOverrides {
     InitOverrides() {
         for (auto& row : g_override)
+            for (auto& v : row) v.store(-1);
+        for (auto& row : g_p2_override)
             for (auto& v : row) v.store(-1);
     }
 } g_init_overrides;
@@ -38,6 +41,14 @@ int fft_split(int dtype, int lgN) {
     return o >= 0 ? o : table_split(dt, lgN);
 }
 
+int fft_p2_variant(int dtype, int lgN, int lg1) {
+    const int dt = dtype == MR1L_C128 ? 1 : 0;
+    if (lgN <= kSmallMaxLg || lgN > kMaxLgN) return 0;
+    const int o = g_p2_override[dt][lgN].load();
+    const int v = o >= 0 ? o : kTunedP2[dt][lgN];
+    return p2_variant_compiled(lgN, lg1, v) ? v : 0;
+}
+
 int64_t work_limit_bytes() { return g_work_limit.load(); }
 bool batch_inblock_enabled() { return g_inblock.load() != 0; }
 
@@ -57,6 +68,26 @@ extern "C" mr1l_status mr1l_batch_inblock(int enable, int* current) {
     clear_error();
     if (enable >= 0) g_inblock.store(enable ? 1 : 0);
     if (current) *current = g_inblock.load();
+    return MR1L_OK;
+}
+
+extern "C" mr1l_status mr1l_fft_p2_variant(mr1l_dtype dtype, int lgN, int variant, int* current) {
+    clear_error();
+    if ((dtype != MR1L_C64 && dtype != MR1L_C128) || lgN <= kSmallMaxLg || lgN > kMaxLgN || variant > 3) {
+        set_error("mr1l_fft_p2_variant: dtype, length (2^13 .. 2^24) or variant (0 .. 3) out of range");
+        return MR1L_ERR_ARG;
+    }
+    const int dt = dtype == MR1L_C128 ? 1 : 0;
+    if (variant >= 0) {
+        if (!p2_variant_compiled(lgN, fft_split(dtype, lgN), variant)) {
+            set_error("mr1l_fft_p2_variant: variant not compiled for this length and its current split");
+            return MR1L_ERR_ARG;
+        }
+        g_p2_override[dt][lgN].store(variant);
+    } else if (variant < -1) {
+        g_p2_override[dt][lgN].store(-1);
+    }
+    if (current) *current = fft_p2_variant(dtype, lgN, fft_split(dtype, lgN));
     return MR1L_OK;
 }
 

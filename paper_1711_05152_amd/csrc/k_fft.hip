@@ -362,20 +362,10 @@ __device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw)
 // A tile holds NSEQ sequences of 2^LGN values (NSEQ * 2^LGN = 4096): every thread owns 16 values
 // of each stage.  The first stage takes its inputs from registers (the caller loads them from
 // global memory in that stage's order) and the last stage leaves its outputs in registers (the
-// caller stores them), so only the exchanges between stages go through LDS.  As few stages as
-// radix 16 allows (ceil(lgn/4)), the bits spread evenly over them: descending radices, or
-// ascending ones when REMF (so a forward transform with REMF and an inverse without meet at
-// stages of the same radix, e.g. 1024 = 8 8 16 | 16 8 8).
-constexpr int n_stages(int lgn) { return (lgn + 3) / 4; }
-constexpr int stage_lr(int lgn, int i, bool remf) {
-    return remf ? (i >= n_stages(lgn) - lgn % n_stages(lgn) ? lgn / n_stages(lgn) + 1 : lgn / n_stages(lgn))
-                : (i < lgn % n_stages(lgn) ? lgn / n_stages(lgn) + 1 : lgn / n_stages(lgn));
-}
-constexpr int stage_lgns(int lgn, int i, bool remf) {
-    int s = 0;
-    for (int k = 0; k < i; ++k) s += stage_lr(lgn, k, remf);
-    return s;
-}
+// caller stores them), so only the exchanges between stages go through LDS.  The radix schedule
+// (REMF: the radix order of stage_lr in common.h) distributes the bits over the stages; which
+// schedule a stage-2 length uses is one of the choices of the autotuner.
+
 constexpr int kVals = (1 << kTileLg) / kThreads;   // values per thread (16)
 
 // butterfly u of this thread in a stage with 2^LGNB butterflies per sequence: (sequence b, index j).
@@ -393,7 +383,7 @@ __device__ __forceinline__ void bfly(int u, int& b, int& j) {
 }
 
 // twiddles and radix-2^LR DFTs of stage I on the registers
-template <typename T, int LGN, int NSEQ, int SIGN, bool REMF, int I, bool BF, int NT = kThreads>
+template <typename T, int LGN, int NSEQ, int SIGN, int REMF, int I, bool BF, int NT = kThreads>
 __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict__ tw) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNS = stage_lgns(LGN, I, REMF);
@@ -432,7 +422,7 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict_
 }
 
 // outputs of stage I -> LDS
-template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF, int NT = kThreads>
+template <typename T, int LGN, int NSEQ, int S, int REMF, int I, bool BF, int NT = kThreads>
 __device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNS = stage_lgns(LGN, I, REMF);
@@ -450,7 +440,7 @@ __device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
 }
 
 // inputs of stage I <- LDS
-template <typename T, int LGN, int NSEQ, int S, bool REMF, int I, bool BF, int NT = kThreads>
+template <typename T, int LGN, int NSEQ, int S, int REMF, int I, bool BF, int NT = kThreads>
 __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNB = LGN - LR;
@@ -467,7 +457,7 @@ __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
 
 // stages I..last; stage I's inputs are in v (mapping BF0 for I = 0, else j-fast); the last stage
 // uses mapping BFL.  On return v holds the last stage's outputs and all LDS reads are done.
-template <typename T, int LGN, int NSEQ, int S, int SIGN, bool REMF, bool BF0, bool BFL, int NT = kThreads, int I = 0>
+template <typename T, int LGN, int NSEQ, int S, int SIGN, int REMF, bool BF0, bool BFL, int NT = kThreads, int I = 0>
 __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __restrict__ tw) {
     constexpr int NS = n_stages(LGN);
     constexpr bool BFI = (I == NS - 1) ? BFL : (I == 0 ? BF0 : false);
@@ -554,11 +544,10 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
 // run by NT threads of 16 values.  Rows of up to 2^10 points take 2048-element tiles: workgroups
 // of two waves instead of four, so each barrier holds fewer waves and the loads of some workgroups
 // on a CU overlap the arithmetic of others (the same waves per CU either way).
-constexpr int kP2TileLg = 11;
-template <int LGN, int LG1>
+template <int LGN, int LG1, int BIG = 0>
 struct RowTile {
     static constexpr int LGN2 = LGN - LG1;
-    static constexpr int TLG = LGN2 + 1 > kP2TileLg ? kTileLg : kP2TileLg;
+    static constexpr int TLG = (BIG || LGN2 + 1 > kP2TileLg) ? kTileLg : kP2TileLg;
     static constexpr int NT = (1 << TLG) / kVals;
     static_assert(TLG >= LGN2 && TLG <= kTileLg, "row tile");
 };
@@ -566,21 +555,22 @@ struct RowTile {
 // One tile = 2^(TLG - LGN2) rows.  CONV: row DFT, multiply by the filter (conjugated for sign +1),
 // inverse row DFT (the forward's last stage and the inverse's first stage have the same radix and
 // hold the same elements, so the product never leaves the registers); else row DFT only.
-template <typename T, int LGN, int LG1, bool CONV>
-__global__ __launch_bounds__((RowTile<LGN, LG1>::NT)) void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work,
-                                                                const cx<T>* __restrict__ filt, int sign,
-                                                                const cx<T>* __restrict__ tw, int rot_in_base,
-                                                                int rot_out_base) {
-    using RT = RowTile<LGN, LG1>;
+template <typename T, int LGN, int LG1, bool CONV, int V = 0>
+__global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1>::NT)) void k_p2(TxArgs a, const int* __restrict__ lat,
+                                                                        cx<T>* work, const cx<T>* __restrict__ filt,
+                                                                        int sign, const cx<T>* __restrict__ tw,
+                                                                        int rot_in_base, int rot_out_base) {
+    using RT = RowTile<LGN, LG1, (V >> 1) & 1>;
+    constexpr int OF = (V & 1) ? 3 : 1, OI = (V & 1) ? 2 : 0;   // forward / inverse radix orders
     constexpr int LGN1 = LG1, LGN2 = LGN - LGN1, NT = RT::NT;
     constexpr int LGR = RT::TLG - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
     constexpr int TPL_LG = LGN - RT::TLG;
-    constexpr int LR0 = stage_lr(LGN2, 0, true), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
+    constexpr int LR0 = stage_lr(LGN2, 0, OF), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
     constexpr int NSI = n_stages(LGN2);
-    constexpr int LRM = stage_lr(LGN2, NSI - 1, true), RM = 1 << LRM;   // forward last = inverse first
+    constexpr int LRM = stage_lr(LGN2, NSI - 1, OF), RM = 1 << LRM;   // forward last = inverse first
     constexpr int LGNBM = LGN2 - LRM;
-    constexpr int LRL = stage_lr(LGN2, NSI - 1, false), RL = 1 << LRL, LGNBL = LGN2 - LRL;
-    static_assert(stage_lr(LGN2, 0, false) == LRM, "the forward's last and the inverse's first stage must match");
+    constexpr int LRL = stage_lr(LGN2, NSI - 1, OI), RL = 1 << LRL, LGNBL = LGN2 - LRL;
+    static_assert(stage_lr(LGN2, 0, OI) == LRM, "the forward's last and the inverse's first stage must match");
     __shared__ cx<T> lds[Padded<(1 << RT::TLG)>::v];
     const int li = blockIdx.x >> TPL_LG;
     const int t = blockIdx.x & ((1 << TPL_LG) - 1);
@@ -609,7 +599,7 @@ __global__ __launch_bounds__((RowTile<LGN, LG1>::NT)) void k_p2(TxArgs a, const 
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[u * R0 + r] = src[(j + (r << LGNB0) + rin) & (N2 - 1)];
     }
-    fft_regs<T, LGN2, ROWS, N2, -1, true, false, false, NT>(lds, v, tw);
+    fft_regs<T, LGN2, ROWS, N2, -1, OF, false, false, NT>(lds, v, tw);
     if constexpr (CONV) {
         const cx<T>* f = filt + D.filt_off;
 #pragma unroll
@@ -626,7 +616,7 @@ __global__ __launch_bounds__((RowTile<LGN, LG1>::NT)) void k_p2(TxArgs a, const 
                 v[u * RM + r] = sign < 0 ? cmul(v[u * RM + r], fv) : cmulc(v[u * RM + r], fv);
             }
         }
-        fft_regs<T, LGN2, ROWS, N2, +1, false, false, false, NT>(lds, v, tw);
+        fft_regs<T, LGN2, ROWS, N2, +1, OI, false, false, NT>(lds, v, tw);
 #pragma unroll
         for (int u = 0; u < kVals / RL; ++u) {
             int b, j;
@@ -865,10 +855,21 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
     const cx<T>* tw = twiddles<T>(dev);
     with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
         constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
-        using RT = RowTile<lg, l1>;
-        const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG)), (unsigned)a.n_rhs);
-        hipLaunchKernelGGL((k_p2<T, lg, l1, true>), grid, dim3(RT::NT), 0, s, a, g.lat, work, filt, sign, tw, ri,
-                           ro);
+        auto go = [&](auto Vc) {
+            constexpr int V = decltype(Vc)::value;
+            if constexpr (p2_variant_compiled(lg, l1, V)) {
+                using RT = RowTile<lg, l1, (V >> 1) & 1>;
+                const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG)), (unsigned)a.n_rhs);
+                hipLaunchKernelGGL((k_p2<T, lg, l1, true, V>), grid, dim3(RT::NT), 0, s, a, g.lat, work, filt, sign,
+                                   tw, ri, ro);
+            }
+        };
+        switch (p2_variant_compiled(lg, l1, g.p2v) ? g.p2v : 0) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 3: go(std::integral_constant<int, 3>{}); break;
+            default: go(std::integral_constant<int, 0>{}); break;
+        }
     });
 }
 

@@ -336,6 +336,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
             g.lgN = spans[i].first;
             g.small = g.lgN <= kSmallMaxLg;
             g.lg1 = P->hdesc[by_len[g.lgN][0]].lgN1;
+            g.p2v = g.small ? 0 : fft_p2_variant(sp.dtype, g.lgN, g.lg1);
             g.nlat = (int)by_len[g.lgN].size();
             g.lat = P->grp_lat.as<int>() + spans[i].second;
             P->groups.push_back(g);

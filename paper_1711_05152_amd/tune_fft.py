@@ -1,12 +1,16 @@
 """Autotuner of the four-step Bluestein schedule; rewrites csrc/fft_schedule_table.h.
 
 Every Bluestein length 2^lgN from 2^13 to 2^24 has three splits compiled (the rule's
-2^lgN1 x 2^(lgN - lgN1) and its neighbours, where both factors stay within 2^4 .. 2^12).  For each
-precision and length this script builds a synthetic plan whose lattices all have that length
-(distinct primes M with 2M - 1 in (2^(lgN-1), 2^lgN], about 2^22 Bluestein points in total),
-times forward + adjoint under every split (mr1l_fft_split), and keeps the fastest one when it
-beats the rule's by more than ``--margin``.  It writes the table, prints one JSON line per length
-and, with ``--report``, a Markdown summary.  Run it on the GPU, then rebuild the library
+2^lgN1 x 2^(lgN - lgN1) and its neighbours, where both factors stay within 2^4 .. 2^12), and
+stage 2 (row DFTs, filter, inverse row DFTs) has up to four variants per split: its radix schedule
+(bits spread evenly over the stages, e.g. 8 8 16 for 1024-point rows, or radix 16 in every stage
+but one, 4 16 16) and its tile size (2048- or 4096-element tiles for rows of up to 2^10 points);
+a variant exists only where it changes the kernel.  For each precision and length this script
+builds a synthetic plan whose lattices all have that length (distinct primes M with 2M - 1 in
+(2^(lgN-1), 2^lgN], about 2^22 Bluestein points in total), times forward + adjoint under every
+(split, variant) (mr1l_fft_split, mr1l_fft_p2_variant), and keeps the fastest when it beats the
+rule's split with variant 0 by more than ``--margin``.  It writes the table, prints one JSON line
+per length and, with ``--report``, a Markdown summary.  Run it on the GPU, then rebuild the library
 (``__graft_entry__.build()``): plans read the table when they are created.
 
     python -m paper_1711_05152_amd.tune_fft [--lengths 13-24] [--dtypes c64,c128] [--report FILE]
@@ -32,6 +36,38 @@ def rule_split(lgn: int) -> int:
 def candidates(lgn: int) -> list[int]:
     r = rule_split(lgn)
     return [s for s in (r - 1, r, r + 1) if 4 <= s <= TILE_LG and 4 <= lgn - s <= TILE_LG]
+
+
+P2_TILE_LG = 11
+
+
+def _n_stages(lg: int) -> int:
+    return (lg + 3) // 4
+
+
+def _stage_lr(lg: int, i: int, order: int) -> int:
+    """Radix (log2) of stage i of a 2^lg-point tile DFT under radix order ``order`` (the library's
+    rule: 1 = bits spread evenly, ascending; 3 = radix 16 but the first stage)."""
+    ns = _n_stages(lg)
+    if order >= 2:
+        return lg - 4 * (ns - 1) if i == (0 if order == 3 else ns - 1) else 4
+    return lg // ns + 1 if i >= ns - lg % ns else lg // ns
+
+
+def p2_variants(lgn: int, split: int) -> list[int]:
+    """Stage-2 variants compiled for this length and split (bit 0 radix schedule, bit 1 big tile)."""
+    lg2 = lgn - split
+    sched = any(_stage_lr(lg2, i, 1) != _stage_lr(lg2, i, 3) for i in range(_n_stages(lg2)))
+    big = lg2 + 1 <= P2_TILE_LG
+    return [v for v in range(4) if (not (v & 1) or sched) and (not (v & 2) or big)]
+
+
+def describe(lgn: int, split: int, v: int) -> str:
+    lg2 = lgn - split
+    order = 3 if v & 1 else 1
+    radices = "x".join(str(1 << _stage_lr(lg2, i, order)) for i in range(_n_stages(lg2)))
+    tile = 4096 if (v & 2) or lg2 + 1 > P2_TILE_LG else 2048
+    return f"{split}/{radices}/{tile}"
 
 
 def _primes_in(lo: int, hi: int, count: int, rng: np.random.Generator) -> np.ndarray:
@@ -94,15 +130,28 @@ def set_split(dtype: str, lgn: int, s: int) -> int:
     return cur.value
 
 
-def write_table(chosen: dict, path: str = TABLE) -> None:
-    rows = []
-    for dt in ("c64", "c128"):
-        vals = [chosen.get((dt, lg), -1) for lg in range(25)]
-        rows.append("    {" + ", ".join(str(v) for v in vals) + "},")
+def set_p2_variant(dtype: str, lgn: int, v: int) -> int:
+    from . import _lib
+    cur = C.c_int(0)
+    _lib.check(_lib.lib().mr1l_fft_p2_variant({"c64": _lib.C64, "c128": _lib.C128}[dtype], lgn, v, C.byref(cur)),
+               "mr1l_fft_p2_variant")
+    return cur.value
+
+
+def write_table(chosen: dict, chosen_p2: dict, path: str = TABLE) -> None:
+    def rows(tab):
+        out = []
+        for dt in ("c64", "c128"):
+            vals = [tab.get((dt, lg), -1) for lg in range(25)]
+            out.append("    {" + ", ".join(str(v) for v in vals) + "},")
+        return "\n".join(out)
     src = ("// Four-step splits of the Bluestein lengths, as measured on MI355X by\n"
            "// paper_1711_05152_amd/tune_fft.py (which rewrites this file): kTunedSplit[dtype][lgN] is lgN1 of\n"
            "// 2^lgN = 2^lgN1 * 2^(lgN - lgN1) for dtype 0 = complex64, 1 = complex128; -1 keeps the rule.\n"
-           "#pragma once\n#include <stdint.h>\nstatic const int8_t kTunedSplit[2][25] = {\n" + "\n".join(rows) + "\n};\n")
+           "#pragma once\n#include <stdint.h>\nstatic const int8_t kTunedSplit[2][25] = {\n" + rows(chosen) + "\n};\n"
+           "// Stage-2 variants (bit 0: radix schedule of orders 3 / 2; bit 1: 4096-element row tiles) chosen by\n"
+           "// the same tuner: kTunedP2[dtype][lgN] for the split of kTunedSplit; -1 keeps variant 0.\n"
+           "static const int8_t kTunedP2[2][25] = {\n" + rows(chosen_p2) + "\n};\n")
     with open(path, "w") as fh:
         fh.write(src)
 
@@ -127,7 +176,7 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
-    chosen, results = {}, []
+    chosen, chosen_p2, results = {}, {}, []
     rng = np.random.default_rng(1711051524)
     for dtype in args.dtypes.split(","):
         for lgn in parse_lengths(args.lengths):
@@ -135,20 +184,26 @@ def main(argv=None) -> int:
             ms = {}
             for s in candidates(lgn):
                 set_split(dtype, lgn, s)
-                ms[s] = time_split(freqs, M, z, dtype, args.reps)
+                for v in p2_variants(lgn, s):
+                    set_p2_variant(dtype, lgn, v)
+                    ms[(s, v)] = time_split(freqs, M, z, dtype, args.reps)
+                set_p2_variant(dtype, lgn, -2)
             set_split(dtype, lgn, -1)
-            r = rule_split(lgn)
+            r = (rule_split(lgn), 0)
             best = min(ms, key=ms.get)
             pick = best if ms[best] < (1.0 - args.margin) * ms[r] else r
-            if pick != r:
-                chosen[(dtype, lgn)] = pick
+            if pick[0] != r[0]:
+                chosen[(dtype, lgn)] = pick[0]
+            if pick[1] != 0:
+                chosen_p2[(dtype, lgn)] = pick[1]
             row = {"dtype": dtype, "lgN": lgn, "L": len(M), "M_range": [int(M.min()), int(M.max())],
-                   "ms_fwd_adj": {str(k): round(v, 5) for k, v in ms.items()}, "rule": r, "chosen": pick,
+                   "ms_fwd_adj": {describe(lgn, *k): round(v, 5) for k, v in ms.items()},
+                   "rule": describe(lgn, *r), "chosen": describe(lgn, *pick),
                    "gain_vs_rule": round(1.0 - ms[pick] / ms[r], 4)}
             results.append(row)
             print(json.dumps(row), flush=True)
     if not args.no_write:
-        write_table(chosen, args.table)
+        write_table(chosen, chosen_p2, args.table)
     if args.report:
         lines = ["# Four-step split autotuning (Bluestein FFT of the multiple rank-1 lattice transform)", "",
                  "Command (from the repository root on one MI355X):", "", "```",
@@ -156,9 +211,12 @@ def main(argv=None) -> int:
                  "```", "",
                  "Forward + adjoint of one plan per row (lattices of exactly that Bluestein length, about 2^22 "
                  "Bluestein points in total), best of 3 x %d calls, in ms per call pair, for every compiled "
-                 "split lgN1 (2^lgN = 2^lgN1 columns x 2^(lgN - lgN1) rows).  A split other than the rule's is "
-                 "kept when it is at least %.0f %% faster." % (args.reps, 100 * args.margin), "",
-                 "| dtype | lgN | L | ms per split | rule | chosen | gain |", "|---|---:|---:|---|---:|---:|---:|"]
+                 "schedule split/radices/tile: the split lgN1 (2^lgN = 2^lgN1 columns x 2^(lgN - lgN1) rows), "
+                 "the radices of stage 2's forward row DFT (the inverse runs them in reverse order) and "
+                 "stage 2's tile in elements.  A schedule other than the rule's split with evenly spread "
+                 "radices and the default tile is kept when it is at least %.0f %% faster."
+                 % (args.reps, 100 * args.margin), "",
+                 "| dtype | lgN | L | ms per schedule | rule | chosen | gain |", "|---|---:|---:|---|---|---|---:|"]
         for r in results:
             cells = ", ".join(f"{k}: {v:.4f}" for k, v in r["ms_fwd_adj"].items())
             lines.append(f"| {r['dtype']} | {r['lgN']} | {r['L']} | {cells} | {r['rule']} | {r['chosen']} | "

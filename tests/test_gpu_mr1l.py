@@ -338,12 +338,13 @@ SPLIT_CASES = [(13, "c64"), (13, "c128"), (15, "c64"), (15, "c128"), (16, "c128"
 
 @pytest.mark.parametrize("lgn,dtype", SPLIT_CASES, ids=[f"lg{a}_{b}" for a, b in SPLIT_CASES])
 def test_every_compiled_split_matches_oracle(lgn, dtype):
-    """Every four-step split compiled for a Bluestein length (the autotuner's candidates) gives the
-    oracle's forward and adjoint; the schedule override is restored afterwards."""
+    """Every four-step schedule compiled for a Bluestein length (the autotuner's candidates: each
+    split, and for each split every stage-2 variant, i.e. radix schedule and tile size) gives the
+    oracle's forward and adjoint; the schedule overrides are restored afterwards."""
     torch = require_gpu()
     import ctypes
     from paper_1711_05152_amd import _lib
-    from paper_1711_05152_amd.tune_fft import candidates
+    from paper_1711_05152_amd.tune_fft import candidates, describe, p2_variants
     lo, hi = (1 << (lgn - 2)) + 1, 1 << (lgn - 1)
     p = transform_problem(rng_for(304, lgn), 1500, 6, 40, 2, lo + (hi - lo) // 2, hi, n_rhs=1)
     ref_c = O.forward(p.freqs, p.M, p.z, p.samples, "paper")
@@ -354,17 +355,24 @@ def test_every_compiled_split_matches_oracle(lgn, dtype):
         for s in candidates(lgn):
             _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, s, ctypes.byref(cur)), "mr1l_fft_split")
             assert cur.value == s
-            print(f"split lg{lgn} {dtype} lgN1={s}", flush=True)
-            plan = _plan(p, dtype)
-            c = plan.forward(_to(torch, p.samples, dtype))
-            yy = plan.adjoint(_to(torch, p.coeffs, dtype))
-            torch.cuda.synchronize()
-            assert_close(c.cpu().numpy(), ref_c, dtype, f"forward split {s}")
-            assert_close(yy.cpu().numpy(), ref_y, dtype, f"adjoint split {s}")
-            del plan
+            for v in p2_variants(lgn, s):
+                _lib.check(_lib.lib().mr1l_fft_p2_variant(dt, lgn, v, ctypes.byref(cur)), "mr1l_fft_p2_variant")
+                assert cur.value == v
+                print(f"schedule lg{lgn} {dtype} {describe(lgn, s, v)}", flush=True)
+                plan = _plan(p, dtype)
+                c = plan.forward(_to(torch, p.samples, dtype))
+                yy = plan.adjoint(_to(torch, p.coeffs, dtype))
+                torch.cuda.synchronize()
+                assert_close(c.cpu().numpy(), ref_c, dtype, f"forward {describe(lgn, s, v)}")
+                assert_close(yy.cpu().numpy(), ref_y, dtype, f"adjoint {describe(lgn, s, v)}")
+                del plan
+            _lib.lib().mr1l_fft_p2_variant(dt, lgn, -2, None)
         with pytest.raises(_lib.Mr1lError):
             _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, 2, None), "mr1l_fft_split")
+        with pytest.raises(_lib.Mr1lError):
+            _lib.check(_lib.lib().mr1l_fft_p2_variant(dt, lgn, 4, None), "mr1l_fft_p2_variant")
     finally:
+        _lib.lib().mr1l_fft_p2_variant(dt, lgn, -2, None)
         _lib.lib().mr1l_fft_split(dt, lgn, -1, None)
 
 
