@@ -168,12 +168,13 @@ mr1l_status mr1l_fft_split(mr1l_dtype dtype, int lgN, int lgN1, int* current);
 /* Variant of stage 2 of the four-step Bluestein FFT (row DFTs, filter, inverse row DFTs) for
  * length 2^lgN: bit 0 selects the radix schedule (radix 16 in every stage but one instead of the
  * bits spread evenly over the stages, e.g. 4 16 16 instead of 8 8 16 for 1024-point rows), bit 1
- * 4096-element row tiles instead of 2048 for rows of up to 2^10 points.  The built-in table
- * (measured by paper_1711_05152_amd/tune_fft.py together with the split) picks one per precision
- * and length.  variant 0..3 sets it for plans of ``dtype`` created from now on (it must be compiled
- * for the length and the split in effect), -1 only queries, -2 restores the table's choice;
- * ``current`` (optional) receives the variant in effect.  Errors: MR1L_ERR_ARG for a length outside
- * 13..24, a variant outside 0..3 or one not compiled for the length and split. */
+ * 4096-element row tiles instead of 2048 for rows of up to 2^10 points, bit 2 eight values per
+ * thread instead of 16 (radices up to 8, e.g. 4 4 8 8, twice the threads; never with bit 0).  The
+ * built-in table (measured by paper_1711_05152_amd/tune_fft.py together with the split) picks one
+ * per precision and length.  variant 0..6 sets it for plans of ``dtype`` created from now on (it
+ * must be compiled for the length and the split in effect), -1 only queries, -2 restores the
+ * table's choice; ``current`` (optional) receives the variant in effect.  Errors: MR1L_ERR_ARG for
+ * a length outside 13..24, a variant outside 0..6 or one not compiled for the length and split. */
 mr1l_status mr1l_fft_p2_variant(mr1l_dtype dtype, int lgN, int variant, int* current);
 
 /* Bound of a plan's Bluestein work area (the intermediate of the prime-length DFTs, one region of

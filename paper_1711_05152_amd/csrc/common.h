@@ -122,40 +122,48 @@ __host__ __device__ constexpr bool split_compiled(int lgN, int lgN1) {
 int fft_split(int dtype, int lgN);   // split plans of this dtype use for Bluestein length 2^lgN
 
 // Radix schedules of the register-resident tile DFTs (stage i of a 2^lgn-point DFT has radix
-// 2^stage_lr(lgn, i, ord)).  As few stages as radix 16 allows (ceil(lgn/4));
-//   ord 0 / 1  bits spread evenly, radices descending (0) or ascending (1);
-//   ord 2 / 3  radix 16 in every stage but one, which takes the remaining bits, last (2) or first (3).
+// 2^stage_lr(lgn, i, ord)).  Every thread holds 2^ord_lgv(ord) values of a tile: 16 (radix up to
+// 16, ceil(lgn/4) stages) or 8 (radix up to 8, ceil(lgn/3) stages, twice the threads);
+//   ord 0 / 1  16 values, bits spread evenly, radices descending (0) or ascending (1);
+//   ord 2 / 3  16 values, radix 16 in every stage but one, which takes the remaining bits, last (2)
+//              or first (3);
+//   ord 4 / 5  8 values, bits spread evenly, descending (4) or ascending (5).
 // A forward DFT with an ascending order and an inverse with the matching descending one meet at
-// stages of the same radix (1024 = 8 8 16 | 16 8 8, or 4 16 16 | 16 16 4).
-constexpr int n_stages(int lgn) { return (lgn + 3) / 4; }
+// stages of the same radix (1024 = 8 8 16 | 16 8 8, 4 16 16 | 16 16 4, or 4 4 8 8 | 8 8 4 4).
+constexpr int ord_lgv(int ord) { return ord >= 4 ? 3 : 4; }
+constexpr int n_stages(int lgn, int ord = 0) { return (lgn + ord_lgv(ord) - 1) / ord_lgv(ord); }
 constexpr int stage_lr(int lgn, int i, int ord) {
-    if (ord >= 2) {
-        const int rem = lgn - 4 * (n_stages(lgn) - 1);
-        return i == (ord == 3 ? 0 : n_stages(lgn) - 1) ? rem : 4;
+    if (ord == 2 || ord == 3) {
+        const int rem = lgn - 4 * (n_stages(lgn, ord) - 1);
+        return i == (ord == 3 ? 0 : n_stages(lgn, ord) - 1) ? rem : 4;
     }
-    return ord == 1 ? (i >= n_stages(lgn) - lgn % n_stages(lgn) ? lgn / n_stages(lgn) + 1 : lgn / n_stages(lgn))
-                    : (i < lgn % n_stages(lgn) ? lgn / n_stages(lgn) + 1 : lgn / n_stages(lgn));
+    const int ns = n_stages(lgn, ord);
+    return (ord == 1 || ord == 5) ? (i >= ns - lgn % ns ? lgn / ns + 1 : lgn / ns)
+                                  : (i < lgn % ns ? lgn / ns + 1 : lgn / ns);
 }
 constexpr int stage_lgns(int lgn, int i, int ord) {
     int s = 0;
     for (int k = 0; k < i; ++k) s += stage_lr(lgn, k, ord);
     return s;
 }
-// the two schedules give different radices for this length
+// the radix-16-major schedule gives different radices than the even one for this length
 constexpr bool schedules_differ(int lgn) {
-    for (int i = 0; i < n_stages(lgn); ++i)
+    for (int i = 0; i < n_stages(lgn, 1); ++i)
         if (stage_lr(lgn, i, 1) != stage_lr(lgn, i, 3)) return true;
     return false;
 }
 
 // Stage 2 takes 2048-element tiles for rows of up to 2^10 points, else 4096.  Its variants, which
 // the autotuner chooses from per length: bit 0, radix orders 3 / 2 instead of 1 / 0 for the forward
-// / inverse row DFTs; bit 1, 4096-element tiles also for the shorter rows.  A variant is compiled
-// only where it changes the kernel.
+// / inverse row DFTs; bit 1, 4096-element tiles also for the shorter rows; bit 2, 8 values per
+// thread (orders 5 / 4, twice the threads per tile; not combined with bit 0).  A variant is
+// compiled only where it changes the kernel.
 constexpr int kP2TileLg = 11;
 constexpr bool p2_variant_compiled(int lgN, int lg1, int v) {
-    return v >= 0 && v <= 3 && (!(v & 1) || schedules_differ(lgN - lg1)) && (!(v & 2) || lgN - lg1 + 1 <= kP2TileLg);
+    return v >= 0 && v <= 6 && !((v & 4) && (v & 1)) && (!(v & 1) || schedules_differ(lgN - lg1)) &&
+           (!(v & 2) || lgN - lg1 + 1 <= kP2TileLg);
 }
+constexpr int kP2Variants = 7;
 int fft_p2_variant(int dtype, int lgN, int lg1);   // the variant plans use for that length and split
 
 // Lattices sharing one Bluestein length, launched together with kernels specialised for it.

@@ -73,8 +73,8 @@ extern "C" mr1l_status mr1l_batch_inblock(int enable, int* current) {
 
 extern "C" mr1l_status mr1l_fft_p2_variant(mr1l_dtype dtype, int lgN, int variant, int* current) {
     clear_error();
-    if ((dtype != MR1L_C64 && dtype != MR1L_C128) || lgN <= kSmallMaxLg || lgN > kMaxLgN || variant > 3) {
-        set_error("mr1l_fft_p2_variant: dtype, length (2^13 .. 2^24) or variant (0 .. 3) out of range");
+    if ((dtype != MR1L_C64 && dtype != MR1L_C128) || lgN <= kSmallMaxLg || lgN > kMaxLgN || variant >= kP2Variants) {
+        set_error("mr1l_fft_p2_variant: dtype, length (2^13 .. 2^24) or variant (0 .. 6) out of range");
         return MR1L_ERR_ARG;
     }
     const int dt = dtype == MR1L_C128 ? 1 : 0;

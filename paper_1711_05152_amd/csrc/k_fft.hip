@@ -359,8 +359,8 @@ __device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw)
 }
 
 // ---- register-resident FFTs for the four-step tiles ------------------------------------------------
-// A tile holds NSEQ sequences of 2^LGN values (NSEQ * 2^LGN = 4096): every thread owns 16 values
-// of each stage.  The first stage takes its inputs from registers (the caller loads them from
+// A tile holds NSEQ sequences of 2^LGN values (NSEQ * 2^LGN = 2048 or 4096): every thread owns 16
+// values of each stage (8 under radix orders 4 / 5).  The first stage takes its inputs from registers (the caller loads them from
 // global memory in that stage's order) and the last stage leaves its outputs in registers (the
 // caller stores them), so only the exchanges between stages go through LDS.  The radix schedule
 // (REMF: the radix order of stage_lr in common.h) distributes the bits over the stages; which
@@ -388,7 +388,7 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict_
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNS = stage_lgns(LGN, I, REMF);
     constexpr int LGNB = LGN - LR;
-    constexpr int NB = kVals / R;
+    constexpr int NB = (1 << ord_lgv(REMF)) / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         int b, j;
@@ -427,7 +427,7 @@ __device__ __forceinline__ void stage_store(cx<T>* buf, const cx<T>* v) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNS = stage_lgns(LGN, I, REMF);
     constexpr int LGNB = LGN - LR;
-    constexpr int NB = kVals / R;
+    constexpr int NB = (1 << ord_lgv(REMF)) / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         int b, j;
@@ -444,7 +444,7 @@ template <typename T, int LGN, int NSEQ, int S, int REMF, int I, bool BF, int NT
 __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
     constexpr int LR = stage_lr(LGN, I, REMF), R = 1 << LR;
     constexpr int LGNB = LGN - LR;
-    constexpr int NB = kVals / R;
+    constexpr int NB = (1 << ord_lgv(REMF)) / R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         int b, j;
@@ -459,7 +459,7 @@ __device__ __forceinline__ void stage_load(const cx<T>* buf, cx<T>* v) {
 // uses mapping BFL.  On return v holds the last stage's outputs and all LDS reads are done.
 template <typename T, int LGN, int NSEQ, int S, int SIGN, int REMF, bool BF0, bool BFL, int NT = kThreads, int I = 0>
 __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __restrict__ tw) {
-    constexpr int NS = n_stages(LGN);
+    constexpr int NS = n_stages(LGN, REMF);
     constexpr bool BFI = (I == NS - 1) ? BFL : (I == 0 ? BF0 : false);
     stage_compute<T, LGN, NSEQ, SIGN, REMF, I, BFI, NT>(v, tw);
     if constexpr (I + 1 < NS) {
@@ -541,14 +541,14 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
 
 // ---- four-step stage 2 -----------------------------------------------------------------------------
 // Row tiles: 2^TLG elements = 2^(TLG - LGN2) rows, at least two (a mirror pair) while LGN2 < 12,
-// run by NT threads of 16 values.  Rows of up to 2^10 points take 2048-element tiles: workgroups
+// run by NT threads of 2^LGV values (16, or 8 with twice the threads).  Rows of up to 2^10 points take 2048-element tiles: workgroups
 // of two waves instead of four, so each barrier holds fewer waves and the loads of some workgroups
 // on a CU overlap the arithmetic of others (the same waves per CU either way).
-template <int LGN, int LG1, int BIG = 0>
+template <int LGN, int LG1, int BIG = 0, int LGV = 4>
 struct RowTile {
     static constexpr int LGN2 = LGN - LG1;
     static constexpr int TLG = (BIG || LGN2 + 1 > kP2TileLg) ? kTileLg : kP2TileLg;
-    static constexpr int NT = (1 << TLG) / kVals;
+    static constexpr int NT = (1 << TLG) >> LGV;
     static_assert(TLG >= LGN2 && TLG <= kTileLg, "row tile");
 };
 
@@ -556,17 +556,18 @@ struct RowTile {
 // inverse row DFT (the forward's last stage and the inverse's first stage have the same radix and
 // hold the same elements, so the product never leaves the registers); else row DFT only.
 template <typename T, int LGN, int LG1, bool CONV, int V = 0>
-__global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1>::NT)) void k_p2(TxArgs a, const int* __restrict__ lat,
-                                                                        cx<T>* work, const cx<T>* __restrict__ filt,
-                                                                        int sign, const cx<T>* __restrict__ tw,
-                                                                        int rot_in_base, int rot_out_base) {
-    using RT = RowTile<LGN, LG1, (V >> 1) & 1>;
-    constexpr int OF = (V & 1) ? 3 : 1, OI = (V & 1) ? 2 : 0;   // forward / inverse radix orders
+__global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1, (V & 4) ? 3 : 4>::NT))
+void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work, const cx<T>* __restrict__ filt, int sign,
+          const cx<T>* __restrict__ tw, int rot_in_base, int rot_out_base) {
+    using RT = RowTile<LGN, LG1, (V >> 1) & 1, (V & 4) ? 3 : 4>;
+    // forward / inverse radix orders
+    constexpr int OF = (V & 4) ? 5 : ((V & 1) ? 3 : 1), OI = (V & 4) ? 4 : ((V & 1) ? 2 : 0);
+    constexpr int VPT = 1 << ord_lgv(OF);
     constexpr int LGN1 = LG1, LGN2 = LGN - LGN1, NT = RT::NT;
     constexpr int LGR = RT::TLG - LGN2, ROWS = 1 << LGR, N2 = 1 << LGN2, N1 = 1 << LGN1;
     constexpr int TPL_LG = LGN - RT::TLG;
     constexpr int LR0 = stage_lr(LGN2, 0, OF), R0 = 1 << LR0, LGNB0 = LGN2 - LR0;
-    constexpr int NSI = n_stages(LGN2);
+    constexpr int NSI = n_stages(LGN2, OF);
     constexpr int LRM = stage_lr(LGN2, NSI - 1, OF), RM = 1 << LRM;   // forward last = inverse first
     constexpr int LGNBM = LGN2 - LRM;
     constexpr int LRL = stage_lr(LGN2, NSI - 1, OI), RL = 1 << LRL, LGNBL = LGN2 - LRL;
@@ -590,9 +591,9 @@ __global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1>::NT)) void k_p2(Tx
         const int p = t * H + (b & (H - 1));
         return b < H ? p : (p == 0 ? N1 / 2 : N1 - p);
     };
-    cx<T> v[kVals];
+    cx<T> v[VPT];
 #pragma unroll
-    for (int u = 0; u < kVals / R0; ++u) {
+    for (int u = 0; u < VPT / R0; ++u) {
         int b, j;
         bfly<LGNB0, ROWS, false, NT>(u, b, j);
         const cx<T>* src = w + ((int64_t)prow(b) << LGN2);
@@ -603,7 +604,7 @@ __global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1>::NT)) void k_p2(Tx
     if constexpr (CONV) {
         const cx<T>* f = filt + D.filt_off;
 #pragma unroll
-        for (int u = 0; u < kVals / RM; ++u) {
+        for (int u = 0; u < VPT / RM; ++u) {
             int b, j;
             bfly<LGNBM, ROWS, false, NT>(u, b, j);
             const int p = t * H + (b & (H - 1));
@@ -618,7 +619,7 @@ __global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1>::NT)) void k_p2(Tx
         }
         fft_regs<T, LGN2, ROWS, N2, +1, OI, false, false, NT>(lds, v, tw);
 #pragma unroll
-        for (int u = 0; u < kVals / RL; ++u) {
+        for (int u = 0; u < VPT / RL; ++u) {
             int b, j;
             bfly<LGNBL, ROWS, false, NT>(u, b, j);
             cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
@@ -627,7 +628,7 @@ __global__ __launch_bounds__((RowTile<LGN, LG1, (V >> 1) & 1>::NT)) void k_p2(Tx
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < kVals / RM; ++u) {
+        for (int u = 0; u < VPT / RM; ++u) {
             int b, j;
             bfly<LGNBM, ROWS, false, NT>(u, b, j);
             cx<T>* dstp = w + ((int64_t)prow(b) << LGN2);
@@ -858,7 +859,7 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
         auto go = [&](auto Vc) {
             constexpr int V = decltype(Vc)::value;
             if constexpr (p2_variant_compiled(lg, l1, V)) {
-                using RT = RowTile<lg, l1, (V >> 1) & 1>;
+                using RT = RowTile<lg, l1, (V >> 1) & 1, (V & 4) ? 3 : 4>;
                 const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG)), (unsigned)a.n_rhs);
                 hipLaunchKernelGGL((k_p2<T, lg, l1, true, V>), grid, dim3(RT::NT), 0, s, a, g.lat, work, filt, sign,
                                    tw, ri, ro);
@@ -868,6 +869,8 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
             case 1: go(std::integral_constant<int, 1>{}); break;
             case 2: go(std::integral_constant<int, 2>{}); break;
             case 3: go(std::integral_constant<int, 3>{}); break;
+            case 4: go(std::integral_constant<int, 4>{}); break;
+            case 6: go(std::integral_constant<int, 6>{}); break;
             default: go(std::integral_constant<int, 0>{}); break;
         }
     });

@@ -2,10 +2,11 @@
 
 Every Bluestein length 2^lgN from 2^13 to 2^24 has three splits compiled (the rule's
 2^lgN1 x 2^(lgN - lgN1) and its neighbours, where both factors stay within 2^4 .. 2^12), and
-stage 2 (row DFTs, filter, inverse row DFTs) has up to four variants per split: its radix schedule
+stage 2 (row DFTs, filter, inverse row DFTs) has up to six variants per split: its radix schedule
 (bits spread evenly over the stages, e.g. 8 8 16 for 1024-point rows, or radix 16 in every stage
-but one, 4 16 16) and its tile size (2048- or 4096-element tiles for rows of up to 2^10 points);
-a variant exists only where it changes the kernel.  For each precision and length this script
+but one, 4 16 16), its values per thread (16, or 8 with radices up to 8, e.g. 4 4 8 8, and twice
+the threads) and its tile size (2048- or 4096-element tiles for rows of up to 2^10 points); a
+variant exists only where it changes the kernel.  For each precision and length this script
 builds a synthetic plan whose lattices all have that length (distinct primes M with 2M - 1 in
 (2^(lgN-1), 2^lgN], about 2^22 Bluestein points in total), times forward + adjoint under every
 (split, variant) (mr1l_fft_split, mr1l_fft_p2_variant), and keeps the fastest when it beats the
@@ -41,33 +42,40 @@ def candidates(lgn: int) -> list[int]:
 P2_TILE_LG = 11
 
 
-def _n_stages(lg: int) -> int:
-    return (lg + 3) // 4
+def _lgv(order: int) -> int:
+    return 3 if order >= 4 else 4
+
+
+def _n_stages(lg: int, order: int = 1) -> int:
+    return (lg + _lgv(order) - 1) // _lgv(order)
 
 
 def _stage_lr(lg: int, i: int, order: int) -> int:
     """Radix (log2) of stage i of a 2^lg-point tile DFT under radix order ``order`` (the library's
-    rule: 1 = bits spread evenly, ascending; 3 = radix 16 but the first stage)."""
-    ns = _n_stages(lg)
-    if order >= 2:
+    rule: 1 = bits spread evenly, ascending, 16 values per thread; 3 = radix 16 but the first
+    stage; 5 = bits spread evenly, ascending, 8 values per thread)."""
+    ns = _n_stages(lg, order)
+    if order in (2, 3):
         return lg - 4 * (ns - 1) if i == (0 if order == 3 else ns - 1) else 4
     return lg // ns + 1 if i >= ns - lg % ns else lg // ns
 
 
 def p2_variants(lgn: int, split: int) -> list[int]:
-    """Stage-2 variants compiled for this length and split (bit 0 radix schedule, bit 1 big tile)."""
+    """Stage-2 variants compiled for this length and split (bit 0 radix schedule, bit 1 big tile,
+    bit 2 eight values per thread)."""
     lg2 = lgn - split
     sched = any(_stage_lr(lg2, i, 1) != _stage_lr(lg2, i, 3) for i in range(_n_stages(lg2)))
     big = lg2 + 1 <= P2_TILE_LG
-    return [v for v in range(4) if (not (v & 1) or sched) and (not (v & 2) or big)]
+    return [v for v in range(7)
+            if not ((v & 4) and (v & 1)) and (not (v & 1) or sched) and (not (v & 2) or big)]
 
 
 def describe(lgn: int, split: int, v: int) -> str:
     lg2 = lgn - split
-    order = 3 if v & 1 else 1
-    radices = "x".join(str(1 << _stage_lr(lg2, i, order)) for i in range(_n_stages(lg2)))
+    order = 5 if v & 4 else (3 if v & 1 else 1)
+    radices = "x".join(str(1 << _stage_lr(lg2, i, order)) for i in range(_n_stages(lg2, order)))
     tile = 4096 if (v & 2) or lg2 + 1 > P2_TILE_LG else 2048
-    return f"{split}/{radices}/{tile}"
+    return f"{split}/{radices}/{tile}" + ("/8v" if v & 4 else "")
 
 
 def _primes_in(lo: int, hi: int, count: int, rng: np.random.Generator) -> np.ndarray:
@@ -149,8 +157,9 @@ def write_table(chosen: dict, chosen_p2: dict, path: str = TABLE) -> None:
            "// paper_1711_05152_amd/tune_fft.py (which rewrites this file): kTunedSplit[dtype][lgN] is lgN1 of\n"
            "// 2^lgN = 2^lgN1 * 2^(lgN - lgN1) for dtype 0 = complex64, 1 = complex128; -1 keeps the rule.\n"
            "#pragma once\n#include <stdint.h>\nstatic const int8_t kTunedSplit[2][25] = {\n" + rows(chosen) + "\n};\n"
-           "// Stage-2 variants (bit 0: radix schedule of orders 3 / 2; bit 1: 4096-element row tiles) chosen by\n"
-           "// the same tuner: kTunedP2[dtype][lgN] for the split of kTunedSplit; -1 keeps variant 0.\n"
+           "// Stage-2 variants (bit 0: radix schedule of orders 3 / 2; bit 1: 4096-element row tiles; bit 2:\n"
+           "// 8 values per thread) chosen by the same tuner: kTunedP2[dtype][lgN] for the split of kTunedSplit;\n"
+           "// -1 keeps variant 0.\n"
            "static const int8_t kTunedP2[2][25] = {\n" + rows(chosen_p2) + "\n};\n")
     with open(path, "w") as fh:
         fh.write(src)
@@ -213,7 +222,7 @@ def main(argv=None) -> int:
                  "Bluestein points in total), best of 3 x %d calls, in ms per call pair, for every compiled "
                  "schedule split/radices/tile: the split lgN1 (2^lgN = 2^lgN1 columns x 2^(lgN - lgN1) rows), "
                  "the radices of stage 2's forward row DFT (the inverse runs them in reverse order) and "
-                 "stage 2's tile in elements.  A schedule other than the rule's split with evenly spread "
+                 "stage 2's tile in elements; /8v marks 8 values per thread instead of 16.  A schedule other than the rule's split with evenly spread "
                  "radices and the default tile is kept when it is at least %.0f %% faster."
                  % (args.reps, 100 * args.margin), "",
                  "| dtype | lgN | L | ms per schedule | rule | chosen | gain |", "|---|---:|---:|---|---|---|---:|"]

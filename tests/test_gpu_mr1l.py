@@ -339,8 +339,8 @@ SPLIT_CASES = [(13, "c64"), (13, "c128"), (15, "c64"), (15, "c128"), (16, "c128"
 @pytest.mark.parametrize("lgn,dtype", SPLIT_CASES, ids=[f"lg{a}_{b}" for a, b in SPLIT_CASES])
 def test_every_compiled_split_matches_oracle(lgn, dtype):
     """Every four-step schedule compiled for a Bluestein length (the autotuner's candidates: each
-    split, and for each split every stage-2 variant, i.e. radix schedule and tile size) gives the
-    oracle's forward and adjoint; the schedule overrides are restored afterwards."""
+    split, and for each split every stage-2 variant, i.e. radix schedule, values per thread and tile
+    size) gives the oracle's forward and adjoint; the schedule overrides are restored afterwards."""
     torch = require_gpu()
     import ctypes
     from paper_1711_05152_amd import _lib
@@ -369,8 +369,9 @@ def test_every_compiled_split_matches_oracle(lgn, dtype):
             _lib.lib().mr1l_fft_p2_variant(dt, lgn, -2, None)
         with pytest.raises(_lib.Mr1lError):
             _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, 2, None), "mr1l_fft_split")
-        with pytest.raises(_lib.Mr1lError):
-            _lib.check(_lib.lib().mr1l_fft_p2_variant(dt, lgn, 4, None), "mr1l_fft_p2_variant")
+        for bad in (5, 7):   # 8 values per thread never combine with the radix-16-major schedule; 7 is out of range
+            with pytest.raises(_lib.Mr1lError):
+                _lib.check(_lib.lib().mr1l_fft_p2_variant(dt, lgn, bad, None), "mr1l_fft_p2_variant")
     finally:
         _lib.lib().mr1l_fft_p2_variant(dt, lgn, -2, None)
         _lib.lib().mr1l_fft_split(dt, lgn, -1, None)
