@@ -795,18 +795,24 @@ def bluestein_alu(stage: str, ms: float, Ns, dtype: str):
     code = _lib.C64 if dtype == "c64" else _lib.C128
     flops = 0.0
     for N in Ns:
-        lg = int(round(math.log2(N)))
         if stage == "bluestein_small":
             flops += 2 * fft_flops(N)
             continue
-        cur = C.c_int(0)
-        if _lib.lib().mr1l_fft_split(code, lg, 0, C.byref(cur)) != 0:
-            return None
-        lg1 = cur.value
+        if N % 3 == 0:
+            # N = 3 * 2^lg: one compiled split, the factor 3 in the stage-2 rows
+            lg = int(round(math.log2(N // 3)))
+            lg1 = max(lg - 11, min((lg + 1) // 2, 8))
+        else:
+            lg = int(round(math.log2(N)))
+            cur = C.c_int(0)
+            if _lib.lib().mr1l_fft_split(code, lg, 0, C.byref(cur)) != 0:
+                return None
+            lg1 = cur.value
+        n1, n2 = 1 << lg1, N >> lg1
         if stage == "bluestein_p2":
-            flops += 2 * fft_flops(1 << (lg - lg1)) * (1 << lg1)
+            flops += 2 * fft_flops(n2) * n1
         elif stage in ("bluestein_p1", "bluestein_p3"):
-            flops += fft_flops(1 << lg1) * (1 << (lg - lg1))
+            flops += fft_flops(n1) * n2
         else:
             return None
     peak = FP32_VECTOR_TFLOPS if dtype == "c64" else FP64_VECTOR_TFLOPS

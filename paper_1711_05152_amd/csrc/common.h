@@ -37,21 +37,22 @@ __device__ inline void sincospi_d(double x, double* s, double* c) { sincospi(x, 
 struct LatDesc {
     int64_t M;         // lattice size M_l
     int64_t samp_off;  // first sample of lattice l inside one right-hand side
-    int64_t work_off;  // first element of its Bluestein work region (length 2^lgN) per rhs
-    int64_t filt_off;  // first element of its filter spectrum (length 2^lgN)
+    int64_t work_off;  // first element of its Bluestein work region (length N, bl_len) per rhs
+    int64_t filt_off;  // first element of its filter spectrum (length N)
     int64_t bm_off;    // first 32-bit word of its alias bitmaps: seen [bm_words] then multi [bm_words]
     int64_t bm_words;  // ceil(M / 32)
     int64_t zoff;      // first component of z_l in the generating-vector table
     double invM;       // 1 / M
-    int32_t lgN;       // Bluestein length 2^lgN >= 2M - 1
-    int32_t lgN1;      // four-step split: 2^lgN = 2^lgN1 * 2^lgN2 (lgN1 = 0 on the one-block path)
-    int32_t lgN2;
+    int32_t lgN;       // Bluestein length N = 2^lgN, or 3 * 2^lgN when n3, N >= 2M - 1
+    int32_t lgN1;      // four-step split: N = 2^lgN1 * N2, N2 = 2^lgN2 or 3 * 2^lgN2 (lgN1 = 0 on
+    int32_t lgN2;      //   the one-block path)
     int32_t small;     // 1: the whole Bluestein convolution runs in one workgroup
     int32_t rt0;       // fused residue/histogram pass: first ResTile of this lattice
     int32_t rtn;       //   and their number
     int32_t tx;        // transform the lattice belongs to
-    int32_t pad_;
+    int32_t n3;        // 1: N = 3 * 2^lgN (the factor 3 sits in the stage-2 rows)
 };
+__host__ __device__ inline int64_t bl_len(const LatDesc& D) { return (int64_t)(D.n3 ? 3 : 1) << D.lgN; }
 
 // One entry per independent transform of a plan (a plain plan has one; a batched plan many).
 // Its frequencies are [foff, foff + fn) of the plan's frequency table and of every coefficient
@@ -121,6 +122,18 @@ __host__ __device__ constexpr bool split_compiled(int lgN, int lgN1) {
 }
 int fft_split(int dtype, int lgN);   // split plans of this dtype use for Bluestein length 2^lgN
 
+// Bluestein lengths N = 3 * 2^lgN (lgN in [kMinLg3, kMaxLg3]) take the place of 2^(lgN + 2) for the
+// lattices of a plan in that class when all of them have 2M - 1 <= N: 25 % fewer points.  Their split
+// puts the factor 3 into the stage-2 rows, N = 2^lgN1 * 3 * 2^(lgN - lgN1), with one compiled
+// split per length: rows of at most 3 * 2^11 points and at least 16 columns per stage-1/3 tile.
+constexpr int kMinLg3 = 12, kMaxLg3 = 22;
+constexpr int kGroupStreams = 3;   // extra streams of a plan for concurrent Bluestein groups
+__host__ __device__ constexpr int split3_lgN1(int lgN) {
+    return (lgN - 11) > ((lgN + 1) / 2 < 8 ? (lgN + 1) / 2 : 8) ? (lgN - 11) : ((lgN + 1) / 2 < 8 ? (lgN + 1) / 2 : 8);
+}
+// plans of this dtype created now may turn the power-of-two class 2^lg into 3 * 2^(lg - 2)
+bool fft_smooth_class(int dtype, int lg);
+
 // Radix schedules of the register-resident tile DFTs (stage i of a 2^lgn-point DFT has radix
 // 2^stage_lr(lgn, i, ord)).  Every thread holds 2^ord_lgv(ord) values of a tile: 16 (radix up to
 // 16, ceil(lgn/4) stages) or 8 (radix up to 8, ceil(lgn/3) stages, twice the threads);
@@ -169,7 +182,8 @@ int fft_p2_variant(int dtype, int lgN, int lg1);   // the variant plans use for 
 // Lattices sharing one Bluestein length, launched together with kernels specialised for it.
 struct FftGroup {
     int lgN;
-    int lg1;          // four-step split 2^lgN = 2^lg1 * 2^(lgN - lg1) (0 on the one-block path)
+    int n3;           // 1: length 3 * 2^lgN
+    int lg1;          // four-step split N = 2^lg1 * N / 2^lg1 (0 on the one-block path)
     int p2v;          // stage-2 variant (radix schedule, tile size) the autotuner chose
     int small;        // one-block path (lgN <= kSmallMaxLg)
     int nlat;

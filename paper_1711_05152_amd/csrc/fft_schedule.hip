@@ -27,6 +27,7 @@ struct InitOverrides {
 constexpr int64_t kDefaultWorkLimit = (int64_t)4 << 30;
 std::atomic<int64_t> g_work_limit{kDefaultWorkLimit};
 std::atomic<int> g_inblock{1};
+std::atomic<int> g_smooth{1};
 
 int table_split(int dt, int lgN) {
     const int t = kTunedSplit[dt][lgN];
@@ -51,6 +52,11 @@ int fft_p2_variant(int dtype, int lgN, int lg1) {
 
 int64_t work_limit_bytes() { return g_work_limit.load(); }
 bool batch_inblock_enabled() { return g_inblock.load() != 0; }
+bool fft_smooth_class(int dtype, int lg) {
+    const int m = g_smooth.load();
+    if (lg < kMinLg3 + 2 || lg > kMaxLg3 + 2) return false;
+    return m == 2 || (m == 1 && kTunedSmooth[dtype == MR1L_C128 ? 1 : 0][lg] == 1);
+}
 
 }  // namespace mr1l
 
@@ -68,6 +74,17 @@ extern "C" mr1l_status mr1l_batch_inblock(int enable, int* current) {
     clear_error();
     if (enable >= 0) g_inblock.store(enable ? 1 : 0);
     if (current) *current = g_inblock.load();
+    return MR1L_OK;
+}
+
+extern "C" mr1l_status mr1l_fft_smooth(int enable, int* current) {
+    clear_error();
+    if (enable > 2) {
+        set_error("mr1l_fft_smooth: mode 0 (powers of two), 1 (measured table) or 2 (every class)");
+        return MR1L_ERR_ARG;
+    }
+    if (enable >= 0) g_smooth.store(enable);
+    if (current) *current = g_smooth.load();
     return MR1L_OK;
 }
 

@@ -2,8 +2,9 @@
 // length M_l per lattice) via Bluestein's chirp-z identity
 //     jm = (j^2 + m^2 - (m - j)^2) / 2,
 //     X[m] = e^{s i pi m^2/M} sum_j (x[j] e^{s i pi j^2/M}) e^{-s i pi (m-j)^2/M},
-// i.e. a cyclic convolution of length N = 2^lgN >= 2M - 1 computed with power-of-two FFTs.
-// Chirp phases are reduced exactly in integers (j^2 mod 2M) before sin/cos.
+// i.e. a cyclic convolution of length N >= 2M - 1: N = 2^lgN, or N = 3 * 2^lgN where that is shorter
+// (the factor 3 then sits in the rows of stage 2, below).  Chirp phases are reduced exactly in
+// integers (j^2 mod 2M) before sin/cos.
 //
 // Two code paths:
 //  * one-block path (N <= 4096): one workgroup holds the whole convolution in LDS;
@@ -31,7 +32,9 @@
 namespace mr1l {
 
 // ---- twiddle tables --------------------------------------------------------------------------------
-// tw[m] = e^{-2 pi i m/4096} (m < 4096), tw[4096 + m] = e^{-2 pi i m/2^24} (m < 4096).
+// tw[m] = e^{-2 pi i m/4096} (m < 4096), tw[4096 + m] = e^{-2 pi i m/2^24} (m < 4096),
+// tw[kTw3Off + m] = e^{-2 pi i m/(3 * 2^11)} (m < 2^11: the radix-3 twiddles of rows of 3 * 2^k points).
+constexpr int kTw3Off = 8192, kTw3Lg = 11;
 static std::mutex g_tw_mu;
 static std::map<std::pair<int, int>, void*> g_tw;
 
@@ -48,7 +51,7 @@ const cx<T>* twiddles(int device) {
     auto key = std::make_pair(device, (int)sizeof(T));
     auto it = g_tw.find(key);
     if (it != g_tw.end()) return (const cx<T>*)it->second;
-    std::vector<cx<T>> h(8192);
+    std::vector<cx<T>> h(kTw3Off + (1 << kTw3Lg));
     for (int m = 0; m < 4096; ++m) {
         double c, s;
         // exact values at multiples of pi/2
@@ -62,6 +65,11 @@ const cx<T>* twiddles(int device) {
         h[m] = make_cx<T>((T)c, (T)s);
         host_cispi2(m, 16777216.0L, &c, &s);
         h[4096 + m] = make_cx<T>((T)c, (T)s);
+    }
+    for (int m = 0; m < (1 << kTw3Lg); ++m) {
+        double c, s;
+        host_cispi2(m, 3.0L * (1 << kTw3Lg), &c, &s);
+        h[kTw3Off + m] = make_cx<T>((T)c, (T)s);
     }
     void* d = nullptr;
     if (hipMalloc(&d, h.size() * sizeof(cx<T>)) != hipSuccess) return nullptr;
@@ -138,6 +146,28 @@ __device__ __forceinline__ cx<T> tw_pow2(uint32_t e, int lgN, const cx<T>* ph) {
         sincospi(x, &s, &c);
         return {c, s};
     }
+}
+
+// e^{-2 pi i e / (3 * 2^lgN)} for 0 <= e < 3 * 2^lgN: the numerator is exact, the division by 3 one
+// rounding in double, then the same table + small-angle rotation (single) or sincospi (double)
+template <typename T>
+__device__ __forceinline__ cx<T> tw_n3(uint32_t e, int lgN, const cx<T>* ph) {
+    if constexpr (sizeof(T) == 4) {
+        const double tau = ldexp((double)e, kPhLg - lgN) * (1.0 / 3.0);   // turns of 1/256
+        const double id = rint(tau);
+        return tw_rot(ph, (int)id, (float)(tau - id) * (float)(6.283185307179586 / (1 << kPhLg)));
+    } else {
+        T s, c;
+        sincospi(-ldexp((double)e, 1 - lgN) / 3.0, &s, &c);
+        return {c, s};
+    }
+}
+
+// e^{-2 pi i e / N} for the four-step length N = F3 * 2^lgN
+template <typename T, int F3>
+__device__ __forceinline__ cx<T> tw_len(uint32_t e, int lgN, const cx<T>* ph) {
+    if constexpr (F3 == 1) return tw_pow2<T>(e, lgN, ph);
+    else return tw_n3<T>(e, lgN, ph);
 }
 
 // e^{sign i pi (n^2 mod 2M)/M}
@@ -473,11 +503,12 @@ __device__ __forceinline__ void fft_regs(cx<T>* buf, cx<T>* v, const cx<T>* __re
 }
 
 // ---- four-step stage 1 -----------------------------------------------------------------------------
-// One tile = C = 2^(12 - LGN1) columns of the N1 x N2 arrangement; tiles per lattice 2^(LGN - 12).
+// One tile = C columns of the N1 x N2 arrangement (N = F3 * 2^LGN, N1 = 2^LGN1, N2 = F3 * 2^LGN2);
+// tiles per lattice N / 2^TLG.
 // SRC 0: x = samples * chirp, 1: x = work (bins) * chirp, 2: x = work as is (all N entries),
 // 3: x = work (bins) * chirp where the alias bitmaps mark the bin as holding exactly one frequency,
 // else 0 (the adjoint's scatter writes only those bins).
-template <typename T, int LGN, int LG1, int SRC>
+template <typename T, int LGN, int LG1, int SRC, int F3 = 1>
 __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, const int* __restrict__ lat,
                                                             const cx<T>* __restrict__ src, int64_t src_stride,
                                                             cx<T>* work, int sign, const cx<T>* __restrict__ tw,
@@ -486,7 +517,8 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
     constexpr int LGN1 = CT::LGN1, LGN2 = LGN - LGN1;
     constexpr int LGC = CT::LGC, C = CT::C, N1 = 1 << LGN1, NT = CT::NT;
     constexpr int S = N1 + 1;
-    constexpr int TPL_LG = LGN - CT::TLG;
+    constexpr int TPL = F3 << (LGN - CT::TLG);   // tiles per lattice
+    constexpr int N2 = F3 << LGN2;
     constexpr int NS = n_stages(LGN1);
     constexpr int LR0 = stage_lr(LGN1, 0, true), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
     constexpr int LRL = stage_lr(LGN1, NS - 1, true), RL = 1 << LRL, LGNBL = LGN1 - LRL;
@@ -494,24 +526,28 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
     __shared__ cx<T> ph[PhaseTab<T>::n];
     phase_fill<T>(ph);
     __syncthreads();
-    const int li = blockIdx.x >> TPL_LG;
-    const int c0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGC;
+    const int li = blockIdx.x / TPL;
+    const int c0 = (blockIdx.x - li * TPL) << LGC;
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     const cx<T>* in = src + rhs * src_stride + (SRC == 0 ? D.samp_off : D.work_off);
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
-    const int64_t nvalid = (SRC == 2) ? ((int64_t)1 << LGN) : D.M;
+    const int64_t nvalid = (SRC == 2) ? ((int64_t)F3 << LGN) : D.M;
     const int rot = SRC == 0 ? Rot<T, LGN, LG1>::of(rot_base, rhs, src_stride, D.samp_off) : 0;
-    constexpr int N2M = (1 << LGN2) - 1;
+    // column n2 of tile column col: (c0 + col - rot) mod N2, c0 + col < N2 and rot < C
+    auto colv = [&](int col) -> int {
+        const int x = c0 + col - rot;
+        return x < 0 ? x + N2 : x;
+    };
     cx<T> v[kVals];
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int col, j;
         bfly<LGNB0, C, true, NT>(u, col, j);
-        const int n2 = (c0 + col - rot) & N2M;
+        const int n2 = colv(col);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            const int64_t n = ((int64_t)(j + (r << LGNB0)) << LGN2) + n2;
+            const int64_t n = (int64_t)(j + (r << LGNB0)) * N2 + n2;
             cx<T> x = {(T)0, (T)0};
             if (n < nvalid) {
                 x = in[n];
@@ -527,13 +563,14 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
     for (int u = 0; u < kVals / RL; ++u) {
         int col, j;
         bfly<LGNBL, C, true, NT>(u, col, j);
-        const int n2 = (c0 + col - rot) & N2M;
-        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
-        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNBL) & ((1 << LGN) - 1)), LGN, ph);
+        const int n2 = colv(col);
+        // n2 j and n2 2^LGNBL are below N (n2 < N2, j and 2^LGNBL below N1)
+        cx<T> wk = tw_len<T, F3>((uint32_t)(n2 * j), LGN, ph);
+        const cx<T> ws = tw_len<T, F3>((uint32_t)(n2 << LGNBL), LGN, ph);
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k1 = j + (r << LGNBL);
-            w[((int64_t)k1 << LGN2) + c0 + col] = cmul(v[u * RL + r], wk);
+            w[(int64_t)k1 * N2 + c0 + col] = cmul(v[u * RL + r], wk);
             wk = cmul(wk, ws);
         }
     }
@@ -638,8 +675,138 @@ void k_p2(TxArgs a, const int* __restrict__ lat, cx<T>* work, const cx<T>* __res
     }
 }
 
+// ---- stage 2 for N = 3 * 2^LGN ---------------------------------------------------------------------
+// Rows of N2 = 3Q points, Q = 2^LGN2.  Decimation in time by 3: the row DFT is three Q-point DFTs
+// Y_s of x[3m + s] (register tile DFTs over the 3 ROWS sequences of a tile, loaded straight from
+// the row) and one radix-3 pass,
+//   X[k + tQ] = sum_s e^{-2 pi i s k/(3Q)} Y_s[k] e^{-2 pi i s t/3}      (k < Q, t < 3),
+// done in LDS together with the filter product and the inverse radix-3 pass; the inverse Q-point
+// DFTs then leave x[3m + s] in registers for the store.  A tile holds 3 * 2^TLG3 elements: ROWS =
+// 2^(TLG3 - LGN2) rows, mirror pairs as in stage 2 above.
+template <int LGN, int LG1>
+struct RowTile3 {
+    static constexpr int LGN2 = LGN - LG1;
+    static constexpr int TLG3 = LGN2 > 10 ? LGN2 : 10;
+    static constexpr int ELEMS = 3 << TLG3;
+    static constexpr int NT = ELEMS / 16;
+    static_assert(LGN2 >= 4 && LGN2 <= 11 && NT <= 1024, "row tile of stage 2 for N = 3 * 2^LGN");
+};
+
+// 3-point DFT with e^{SIGN 2 pi i/3}
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft3(cx<T> y0, cx<T> y1, cx<T> y2, cx<T>& x0, cx<T>& x1, cx<T>& x2) {
+    const T h = (T)0.866025403784438646763723170752936183;   // sqrt(3)/2
+    const cx<T> p = y1 + y2, q = y1 - y2;
+    const cx<T> m = {y0.x - (T)0.5 * p.x, y0.y - (T)0.5 * p.y};
+    const cx<T> r = mul_si<T, SIGN>(cx<T>{h * q.x, h * q.y});   // SIGN i (sqrt(3)/2) (y1 - y2)
+    x0 = y0 + p;
+    x1 = m + r;
+    x2 = m - r;
+}
+
+template <typename T, int LGN, int LG1, bool CONV>
+__global__ __launch_bounds__((RowTile3<LGN, LG1>::NT)) void k_p2r3(TxArgs a, const int* __restrict__ lat, cx<T>* work,
+                                                            const cx<T>* __restrict__ filt, int sign,
+                                                            const cx<T>* __restrict__ tw, int rot_in_base,
+                                                            int rot_out_base) {
+    using RT = RowTile3<LGN, LG1>;
+    constexpr int OF = 1, OI = 0;
+    constexpr int LGQ = RT::LGN2, Q = 1 << LGQ, N2 = 3 * Q, N1 = 1 << LG1, NT = RT::NT;
+    constexpr int LGR = RT::TLG3 - LGQ, ROWS = 1 << LGR, NSEQ = 3 * ROWS;
+    constexpr int TPL_LG = LGN - RT::TLG3;   // tiles per lattice: N / (3 * 2^TLG3)
+    constexpr int LR0 = stage_lr(LGQ, 0, OF), R0 = 1 << LR0, LGNB0 = LGQ - LR0;
+    constexpr int NSF = n_stages(LGQ, OF), NSI = n_stages(LGQ, OI);
+    constexpr int LRL = stage_lr(LGQ, NSI - 1, OI), RL = 1 << LRL, LGNBL = LGQ - LRL;
+    constexpr int NTRI = (ROWS * Q + NT - 1) / NT;   // radix-3 points per thread (16/3 rounded up)
+    __shared__ cx<T> lds[Padded<RT::ELEMS>::v];
+    const int li = blockIdx.x >> TPL_LG;
+    const int t = blockIdx.x & ((1 << TPL_LG) - 1);
+    const LatDesc D = a.desc[lat[li]];
+    const int64_t rhs = blockIdx.y;
+    cx<T>* w = work + rhs * a.work_stride + D.work_off;
+    const int rin = rot_in_base < 0 ? 0 : Rot<T, LGN, LG1>::of(rot_in_base, rhs, a.samp_stride, D.samp_off);
+    const int rout = rot_out_base < 0 ? 0 : Rot<T, LGN, LG1>::of(rot_out_base, rhs, a.samp_stride, D.samp_off);
+    constexpr int H = ROWS > 1 ? ROWS / 2 : 1;
+    auto prow = [&](int row) -> int {
+        if constexpr (ROWS == 1) return t;
+        const int p = t * H + (row & (H - 1));
+        return row < H ? p : (p == 0 ? N1 / 2 : N1 - p);
+    };
+    // sequence b = s ROWS + row: x[3m + s] of tile row `row`, m < Q (stage 1's rotation undone)
+    cx<T> v[16];
+#pragma unroll
+    for (int u = 0; u < 16 / R0; ++u) {
+        int b, j;
+        bfly<LGNB0, NSEQ, false, NT>(u, b, j);
+        const int sres = b >> LGR, row = b & (ROWS - 1);
+        const cx<T>* src = w + (int64_t)prow(row) * N2;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int e = 3 * (j + (r << LGNB0)) + sres + rin;   // < 2 N2
+            v[u * R0 + r] = src[e >= N2 ? e - N2 : e];
+        }
+    }
+    fft_regs<T, LGQ, NSEQ, Q, -1, OF, false, false, NT>(lds, v, tw);
+    // every LDS read of the DFTs is done (fft_regs ends with a barrier after its last load)
+    stage_store<T, LGQ, NSEQ, Q, OF, NSF - 1, false, NT>(lds, v);   // Y_s[k] at (s ROWS + row) Q + k
+    __syncthreads();
+    const cx<T>* f = CONV ? filt + D.filt_off : nullptr;
+#pragma unroll
+    for (int kk = 0; kk < NTRI; ++kk) {
+        const int e = threadIdx.x + kk * NT;
+        if (e >= ROWS * Q) break;
+        const int row = e >> LGQ, k = e & (Q - 1);
+        const int i0 = pidx(row * Q + k), i1 = pidx((ROWS + row) * Q + k), i2 = pidx((2 * ROWS + row) * Q + k);
+        const cx<T> w1 = tw[kTw3Off + (k << (kTw3Lg - LGQ))];   // e^{-2 pi i k/(3Q)}
+        const cx<T> w2 = cmul(w1, w1);
+        cx<T> x0, x1, x2;
+        dft3<T, -1>(lds[i0], cmul(lds[i1], w1), cmul(lds[i2], w2), x0, x1, x2);
+        if constexpr (CONV) {
+            // filter B[k1][k2] = B[N1 - k1][N2 - 1 - k2] (0 < k1 < N1): a mirror row reads its partner's
+            const int p = ROWS > 1 ? t * H + (row & (H - 1)) : t;
+            const bool mirror = ROWS > 1 && row >= H && p != 0;
+            const cx<T>* fr = f + (int64_t)(mirror ? p : prow(row)) * N2;
+            const cx<T> f0 = fr[mirror ? N2 - 1 - k : k];
+            const cx<T> f1 = fr[mirror ? N2 - 1 - (k + Q) : k + Q];
+            const cx<T> f2 = fr[mirror ? N2 - 1 - (k + 2 * Q) : k + 2 * Q];
+            x0 = sign < 0 ? cmul(x0, f0) : cmulc(x0, f0);
+            x1 = sign < 0 ? cmul(x1, f1) : cmulc(x1, f1);
+            x2 = sign < 0 ? cmul(x2, f2) : cmulc(x2, f2);
+            cx<T> z0, z1, z2;
+            dft3<T, +1>(x0, x1, x2, z0, z1, z2);
+            lds[i0] = z0;
+            lds[i1] = cmulc(z1, w1);
+            lds[i2] = cmulc(z2, w2);
+        } else {
+            // forward row DFT only (filter construction): natural order, no rotation
+            cx<T>* dstp = w + (int64_t)prow(row) * N2;
+            dstp[k] = x0;
+            dstp[k + Q] = x1;
+            dstp[k + 2 * Q] = x2;
+        }
+    }
+    if constexpr (CONV) {
+        __syncthreads();
+        stage_load<T, LGQ, NSEQ, Q, OI, 0, false, NT>(lds, v);
+        __syncthreads();
+        fft_regs<T, LGQ, NSEQ, Q, +1, OI, false, false, NT>(lds, v, tw);
+#pragma unroll
+        for (int u = 0; u < 16 / RL; ++u) {
+            int b, j;
+            bfly<LGNBL, NSEQ, false, NT>(u, b, j);
+            const int sres = b >> LGR, row = b & (ROWS - 1);
+            cx<T>* dstp = w + (int64_t)prow(row) * N2;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int e = 3 * (j + (r << LGNBL)) + sres + rout;
+                dstp[e >= N2 ? e - N2 : e] = v[u * RL + r];
+            }
+        }
+    }
+}
+
 // ---- four-step stage 3 -----------------------------------------------------------------------------
-template <typename T, int LGN, int LG1, bool TO_SAMPLES>
+template <typename T, int LGN, int LG1, bool TO_SAMPLES, int F3 = 1>
 __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p3(TxArgs a, const int* __restrict__ lat, cx<T>* work,
                                                             cx<T>* dst, int64_t dst_stride, int sign,
                                                             int scale_by_invM, const cx<T>* __restrict__ tw,
@@ -648,7 +815,8 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p3(TxArgs a, con
     constexpr int LGN1 = CT::LGN1, LGN2 = LGN - LGN1;
     constexpr int LGC = CT::LGC, C = CT::C, N1 = 1 << LGN1, NT = CT::NT;
     constexpr int S = N1 + 1;
-    constexpr int TPL_LG = LGN - CT::TLG;
+    constexpr int TPL = F3 << (LGN - CT::TLG);   // tiles per lattice
+    constexpr int N2 = F3 << LGN2;
     constexpr int NS = n_stages(LGN1);
     constexpr int LR0 = stage_lr(LGN1, 0, false), R0 = 1 << LR0, LGNB0 = LGN1 - LR0;
     constexpr int LRL = stage_lr(LGN1, NS - 1, false), RL = 1 << LRL, LGNBL = LGN1 - LRL;
@@ -656,25 +824,28 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p3(TxArgs a, con
     __shared__ cx<T> ph[PhaseTab<T>::n];
     phase_fill<T>(ph);
     __syncthreads();
-    const int li = blockIdx.x >> TPL_LG;
-    const int c0 = (blockIdx.x & ((1 << TPL_LG) - 1)) << LGC;
+    const int li = blockIdx.x / TPL;
+    const int c0 = (blockIdx.x - li * TPL) << LGC;
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
     const int rot = TO_SAMPLES ? Rot<T, LGN, LG1>::of(rot_base, rhs, dst_stride, D.samp_off) : 0;
-    constexpr int N2M = (1 << LGN2) - 1;
+    auto colv = [&](int col) -> int {
+        const int x = c0 + col - rot;
+        return x < 0 ? x + N2 : x;
+    };
     cx<T> v[kVals];
 #pragma unroll
     for (int u = 0; u < kVals / R0; ++u) {
         int col, j;
         bfly<LGNB0, C, true, NT>(u, col, j);
-        const int n2 = (c0 + col - rot) & N2M;
-        cx<T> wk = tw_pow2<T>((uint32_t)(n2 * j), LGN, ph);
-        const cx<T> ws = tw_pow2<T>((uint32_t)((n2 << LGNB0) & ((1 << LGN) - 1)), LGN, ph);
+        const int n2 = colv(col);
+        cx<T> wk = tw_len<T, F3>((uint32_t)(n2 * j), LGN, ph);
+        const cx<T> ws = tw_len<T, F3>((uint32_t)(n2 << LGNB0), LGN, ph);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k1 = j + (r << LGNB0);
-            v[u * R0 + r] = cmulc(w[((int64_t)k1 << LGN2) + c0 + col], wk);
+            v[u * R0 + r] = cmulc(w[(int64_t)k1 * N2 + c0 + col], wk);
             wk = cmul(wk, ws);
         }
     }
@@ -690,7 +861,7 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p3(TxArgs a, con
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int n1 = j + (r << LGNBL);
-            const int64_t n = ((int64_t)n1 << LGN2) + ((c0 + col - rot) & N2M);
+            const int64_t n = (int64_t)n1 * N2 + colv(col);
             if (n < D.M) out[n] = cscale(cmul(v[u * RL + r], chirp<T>(n, D.M, D.invM, sign, ph)), sc);
         }
     }
@@ -744,11 +915,12 @@ __global__ __launch_bounds__(kThreads) void k_small_dft(TxArgs a, const int* __r
     for (int n = threadIdx.x; n < N; n += kThreads) w[n] = lds[pidx(n)];
 }
 
-// b_l[n] = e^{+i pi n^2/M} for 0 <= n < M and at N - n for 0 < n < M, zero elsewhere (double)
+// b_l[n] = e^{+i pi n^2/M} for 0 <= n < M and at N - n for 0 < n < M, zero elsewhere (double);
+// N = bl_len, a power of two or 3 * 2^lgN
 __global__ void k_filter_fill(const LatDesc* __restrict__ desc, int L, cx<double>* tmp) {
     const int l = blockIdx.y;
     const LatDesc D = desc[l];
-    const int64_t N = (int64_t)1 << D.lgN;
+    const int64_t N = bl_len(D);
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         int64_t m = -1;
         if (n < D.M) m = n;
@@ -763,7 +935,7 @@ template <typename T>
 __global__ void k_filter_store(const LatDesc* __restrict__ desc, const cx<double>* __restrict__ tmp, cx<T>* filt) {
     const int l = blockIdx.y;
     const LatDesc D = desc[l];
-    const int64_t N = (int64_t)1 << D.lgN;
+    const int64_t N = bl_len(D);
     const double sc = 1.0 / (double)N;
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const cx<double> v = tmp[D.work_off + n];
@@ -804,6 +976,15 @@ static void with_split(int lgN, int lg1, F&& f) {
     });
 }
 
+// kernels for N = 3 * 2^lgN: f(LG, LG1) with the one compiled split
+template <typename F>
+static void with_len3(int lgN, F&& f) {
+    with_lg<kMinLg3, kMaxLg3>(lgN, [&](auto LG) {
+        constexpr int lg = decltype(LG)::value;
+        f(LG, std::integral_constant<int, split3_lgN1(lg)>{});
+    });
+}
+
 template <typename T>
 void launch_bluestein_small(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src_stride,
                             bool src_is_samples, cx<T>* work, const cx<T>* filt, cx<T>* dst, int64_t dst_stride,
@@ -832,17 +1013,24 @@ void launch_p1(const TxArgs& a, const FftGroup& g, const cx<T>* src, int64_t src
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
-        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+    auto go = [&](auto LG, auto LG1c, auto F3c) {
+        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value, f3 = decltype(F3c)::value;
         using CT = ColTile<T, lg, l1>;
-        const dim3 grid((unsigned)(g.nlat << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
+        const dim3 grid((unsigned)((g.nlat * f3) << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
         if (src_is_samples)
-            hipLaunchKernelGGL((k_p1<T, lg, l1, 0>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, rb);
+            hipLaunchKernelGGL((k_p1<T, lg, l1, 0, f3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw,
+                               rb);
         else if (mask_bins)
-            hipLaunchKernelGGL((k_p1<T, lg, l1, 3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
+            hipLaunchKernelGGL((k_p1<T, lg, l1, 3, f3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw,
+                               0);
         else
-            hipLaunchKernelGGL((k_p1<T, lg, l1, 1>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw, 0);
-    });
+            hipLaunchKernelGGL((k_p1<T, lg, l1, 1, f3>), grid, block, 0, s, a, g.lat, src, src_stride, work, sign, tw,
+                               0);
+    };
+    if (g.n3)
+        with_len3(g.lgN, [&](auto LG, auto LG1c) { go(LG, LG1c, std::integral_constant<int, 3>{}); });
+    else
+        with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) { go(LG, LG1c, std::integral_constant<int, 1>{}); });
 }
 
 template <typename T>
@@ -854,6 +1042,16 @@ void launch_p2(const TxArgs& a, const FftGroup& g, cx<T>* work, const cx<T>* fil
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
+    if (g.n3) {
+        with_len3(g.lgN, [&](auto LG, auto LG1c) {
+            constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+            using RT = RowTile3<lg, l1>;
+            const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG3)), (unsigned)a.n_rhs);
+            hipLaunchKernelGGL((k_p2r3<T, lg, l1, true>), grid, dim3(RT::NT), 0, s, a, g.lat, work, filt, sign, tw,
+                               ri, ro);
+        });
+        return;
+    }
     with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
         constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
         auto go = [&](auto Vc) {
@@ -884,17 +1082,21 @@ void launch_p3(const TxArgs& a, const FftGroup& g, cx<T>* work, cx<T>* dst, int6
     int dev = 0;
     (void)hipGetDevice(&dev);
     const cx<T>* tw = twiddles<T>(dev);
-    with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {
-        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+    auto go = [&](auto LG, auto LG1c, auto F3c) {
+        constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value, f3 = decltype(F3c)::value;
         using CT = ColTile<T, lg, l1>;
-        const dim3 grid((unsigned)(g.nlat << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
+        const dim3 grid((unsigned)((g.nlat * f3) << (lg - CT::TLG)), (unsigned)a.n_rhs), block(CT::NT);
         if (dst_is_samples)
-            hipLaunchKernelGGL((k_p3<T, lg, l1, true>), grid, block, 0, s, a, g.lat, work, dst, dst_stride, sign,
+            hipLaunchKernelGGL((k_p3<T, lg, l1, true, f3>), grid, block, 0, s, a, g.lat, work, dst, dst_stride, sign,
                                (int)scale_by_invM, tw, rb);
         else
-            hipLaunchKernelGGL((k_p3<T, lg, l1, false>), grid, block, 0, s, a, g.lat, work, dst, dst_stride,
+            hipLaunchKernelGGL((k_p3<T, lg, l1, false, f3>), grid, block, 0, s, a, g.lat, work, dst, dst_stride,
                                sign, (int)scale_by_invM, tw, 0);
-    });
+    };
+    if (g.n3)
+        with_len3(g.lgN, [&](auto LG, auto LG1c) { go(LG, LG1c, std::integral_constant<int, 3>{}); });
+    else
+        with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) { go(LG, LG1c, std::integral_constant<int, 1>{}); });
 }
 
 #define MR1L_INST_FFT(T)                                                                                           \
@@ -1104,7 +1306,7 @@ hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cons
     int64_t tot = 0;
     int maxlg = 0;
     for (int l = 0; l < L; ++l) {
-        tot = std::max<int64_t>(tot, hdesc[l].work_off + ((int64_t)1 << hdesc[l].lgN));
+        tot = std::max<int64_t>(tot, hdesc[l].work_off + bl_len(hdesc[l]));
         maxlg = std::max(maxlg, hdesc[l].lgN);
     }
     DevMem tmpm;
@@ -1124,6 +1326,18 @@ hipError_t build_filters(const LatDesc* hdesc, int L, const LatDesc* ddesc, cons
             with_lg<0, kSmallMaxLg>(g.lgN, [&](auto LG) {
                 hipLaunchKernelGGL((k_small_dft<decltype(LG)::value>), dim3(g.nlat), dim3(kThreads), 0, s, a, g.lat,
                                    tmp, tw);
+            });
+        } else if (g.n3) {
+            with_len3(g.lgN, [&](auto LG, auto LG1c) {
+                constexpr int lg = decltype(LG)::value, l1 = decltype(LG1c)::value;
+                using CT = ColTile<double, lg, l1>;
+                using RT = RowTile3<lg, l1>;
+                const dim3 grid1((unsigned)((g.nlat * 3) << (lg - CT::TLG)), 1);
+                const dim3 grid((unsigned)(g.nlat << (lg - RT::TLG3)), 1);
+                hipLaunchKernelGGL((k_p1<double, lg, l1, 2, 3>), grid1, dim3(CT::NT), 0, s, a, g.lat,
+                                   (const cx<double>*)tmp, (int64_t)0, tmp, -1, tw, 0);
+                hipLaunchKernelGGL((k_p2r3<double, lg, l1, false>), grid, dim3(RT::NT), 0, s, a, g.lat, tmp,
+                                   (const cx<double>*)nullptr, -1, tw, -1, -1);
             });
         } else {
             with_split(g.lgN, g.lg1, [&](auto LG, auto LG1c) {

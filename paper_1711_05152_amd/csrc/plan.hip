@@ -20,6 +20,39 @@ void clear_error() { g_err.clear(); }
 static const char* kStageNames[MR1L_NSTAGES] = {"alias_hist", "bluestein_small", "bluestein_p1", "bluestein_p2",
                                                 "bluestein_p3", "gather",        "scatter",      "inblock_small"};
 
+// Streams for the concurrent group pipelines, kept per device between plans (plans of the sparse
+// FFT come and go at every step; creating streams each time would cost more than the transforms).
+// Every stream is created with the default priority.
+namespace {
+std::mutex g_gs_mu;
+std::map<int, std::vector<hipStream_t>> g_gs_free;
+
+hipError_t take_group_streams(int dev, int k, std::vector<hipStream_t>& out) {
+    std::lock_guard<std::mutex> lk(g_gs_mu);
+    auto& f = g_gs_free[dev];
+    while ((int)out.size() < k) {
+        if (!f.empty()) {
+            out.push_back(f.back());
+            f.pop_back();
+            continue;
+        }
+        hipStream_t st;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        out.push_back(st);
+    }
+    return hipSuccess;
+}
+
+void give_group_streams(int dev, std::vector<hipStream_t>& st) {
+    for (hipStream_t x : st) (void)hipStreamSynchronize(x);
+    std::lock_guard<std::mutex> lk(g_gs_mu);
+    auto& f = g_gs_free[dev];
+    f.insert(f.end(), st.begin(), st.end());
+    st.clear();
+}
+}  // namespace
+
 Plan::~Plan() {
     if (side) {
         (void)hipStreamSynchronize(side);
@@ -27,6 +60,9 @@ Plan::~Plan() {
     }
     if (fork) hipEventDestroy(fork);
     if (join) hipEventDestroy(join);
+    if (!gstream.empty()) give_group_streams(device, gstream);
+    for (auto e : gdone) hipEventDestroy(e);
+    if (gstart) hipEventDestroy(gstart);
     for (auto& r : pending) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -64,10 +100,10 @@ static void pack_soa(const int32_t* f, int64_t n, int d, std::vector<char>& out)
 // device, least recently used out first; mr1l_memory_cache empties the device's entries.
 namespace {
 struct FiltKey {
-    int dev, dtype, lgN, lgN1;
+    int dev, dtype, lgN, n3, lgN1;
     int64_t M;
     bool operator<(const FiltKey& o) const {
-        return std::tie(dev, dtype, lgN, lgN1, M) < std::tie(o.dev, o.dtype, o.lgN, o.lgN1, o.M);
+        return std::tie(dev, dtype, lgN, n3, lgN1, M) < std::tie(o.dev, o.dtype, o.lgN, o.n3, o.lgN1, o.M);
     }
 };
 struct FiltEntry {
@@ -115,7 +151,7 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
         std::vector<std::pair<const FiltEntry*, int>> hits;
         for (int l = 0; l < L; ++l) {
             const LatDesc& D = P->hdesc[l];
-            auto it = m.find(FiltKey{device, (int)P->dtype, D.lgN, D.lgN1, D.M});
+            auto it = m.find(FiltKey{device, (int)P->dtype, D.lgN, D.n3, D.lgN1, D.M});
             if (it == m.end()) miss.push_back(l);
             else hits.push_back({&it->second, l});
         }
@@ -123,7 +159,7 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
             std::vector<CopySeg> segs;
             for (auto& h : hits) {
                 const LatDesc& D = P->hdesc[h.second];
-                segs.push_back(CopySeg{h.first->buf.p, filt + D.filt_off, ((uint64_t)1 << D.lgN) * sizeof(cx<T>)});
+                segs.push_back(CopySeg{h.first->buf.p, filt + D.filt_off, (uint64_t)bl_len(D) * sizeof(cx<T>)});
                 const_cast<FiltEntry*>(h.first)->used = ++g_fc_clock;
             }
             return copy_segments(segs.data(), (int)segs.size(), nullptr);
@@ -135,8 +171,8 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
     auto& m = fc_map();
     for (int l : miss) {
         const LatDesc& D = P->hdesc[l];
-        const size_t bytes = ((size_t)1 << D.lgN) * sizeof(cx<T>);
-        const FiltKey key{device, (int)P->dtype, D.lgN, D.lgN1, D.M};
+        const size_t bytes = (size_t)bl_len(D) * sizeof(cx<T>);
+        const FiltKey key{device, (int)P->dtype, D.lgN, D.n3, D.lgN1, D.M};
         if (bytes > kFiltEntryMax || m.count(key)) continue;
         FiltEntry ent;
         if (ent.buf.alloc(bytes) != hipSuccess) {
@@ -252,7 +288,16 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     P->hdesc.resize(L);
     P->samp_off.assign(L + 1, 0);
     int64_t woff = 0, bmoff = 0;
-    std::map<int, std::vector<int>> by_len;   // Bluestein length -> lattices
+    std::map<int, std::vector<int>> by_len;   // Bluestein length (2 lgN + n3) -> lattices
+    // A power-of-two class 2^lg turns into 3 * 2^(lg - 2) only when every lattice of the plan in it
+    // fits (2M - 1 <= 3 * 2^(lg - 2)): a class split over two lengths runs twice the launches, each
+    // with half the tiles, which costs more on the GPU than the 25 % fewer points save.
+    bool n3_class[kMaxLgN + 3];
+    for (int lg = 0; lg < kMaxLgN + 3; ++lg) n3_class[lg] = fft_smooth_class(sp.dtype, lg);
+    for (int l = 0; l < L; ++l) {
+        const int lg = ceil_lg(2 * sp.M[l] - 1);
+        if (lg - 2 >= kMinLg3 && lg - 2 <= kMaxLg3 && (3LL << (lg - 2)) < 2 * sp.M[l] - 1) n3_class[lg] = false;
+    }
     for (int l = 0; l < L; ++l) {
         LatDesc& D = P->hdesc[l];
         D.M = sp.M[l];
@@ -260,17 +305,22 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         D.samp_off = P->samp_off[l];
         P->samp_off[l + 1] = P->samp_off[l] + D.M;
         D.lgN = ceil_lg(2 * D.M - 1);
-        D.small = D.lgN <= kSmallMaxLg;
-        D.lgN1 = D.small ? 0 : fft_split(sp.dtype, D.lgN);
+        D.n3 = 0;
+        if (n3_class[D.lgN]) {
+            D.lgN -= 2;   // N = 3 * 2^(lgN - 2) < 2^lgN still covers 2M - 1
+            D.n3 = 1;
+        }
+        D.small = !D.n3 && D.lgN <= kSmallMaxLg;
+        D.lgN1 = D.small ? 0 : (D.n3 ? split3_lgN1(D.lgN) : fft_split(sp.dtype, D.lgN));
         D.lgN2 = D.lgN - D.lgN1;
         D.work_off = woff;
         D.filt_off = woff;
-        woff += (int64_t)1 << D.lgN;
+        woff += bl_len(D);
         D.bm_words = (D.M + 31) / 32;
         D.bm_off = bmoff;
         bmoff += 2 * D.bm_words;
         D.zoff = (int64_t)l * d;
-        by_len[D.lgN].push_back(l);
+        by_len[2 * D.lgN + D.n3].push_back(l);
     }
     P->sum_M = P->samp_off[L];
     P->work_stride = woff;
@@ -325,7 +375,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     MR1L_HIP_TRY(stg.add(P->z, zred.data(), zred.size() * sizeof(int64_t)));
     {
         std::vector<int> ids;
-        std::vector<std::pair<int, int>> spans;   // (lgN, first index)
+        std::vector<std::pair<int, int>> spans;   // (2 lgN + n3, first index)
         for (auto& kv : by_len) {
             spans.push_back({kv.first, (int)ids.size()});
             ids.insert(ids.end(), kv.second.begin(), kv.second.end());
@@ -333,11 +383,12 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         MR1L_HIP_TRY(stg.add(P->grp_lat, ids.data(), ids.size() * sizeof(int)));
         for (size_t i = 0; i < spans.size(); ++i) {
             FftGroup g;
-            g.lgN = spans[i].first;
-            g.small = g.lgN <= kSmallMaxLg;
-            g.lg1 = P->hdesc[by_len[g.lgN][0]].lgN1;
-            g.p2v = g.small ? 0 : fft_p2_variant(sp.dtype, g.lgN, g.lg1);
-            g.nlat = (int)by_len[g.lgN].size();
+            g.lgN = spans[i].first >> 1;
+            g.n3 = spans[i].first & 1;
+            g.small = !g.n3 && g.lgN <= kSmallMaxLg;
+            g.lg1 = P->hdesc[by_len[spans[i].first][0]].lgN1;
+            g.p2v = (g.small || g.n3) ? 0 : fft_p2_variant(sp.dtype, g.lgN, g.lg1);
+            g.nlat = (int)by_len[spans[i].first].size();
             g.lat = P->grp_lat.as<int>() + spans[i].second;
             P->groups.push_back(g);
         }
@@ -360,6 +411,15 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
                 g.lat = P->sweep_lat.as<int>() + sg.second.first;
                 P->sweep.push_back(g);
             }
+        }
+        int n4 = 0;
+        for (const FftGroup& g : P->sweep) n4 += !g.small;
+        if (n4 >= 2) {
+            const int k = std::min(n4 - 1, kGroupStreams);
+            MR1L_HIP_TRY(take_group_streams(P->device, k, P->gstream));
+            MR1L_HIP_TRY(hipEventCreateWithFlags(&P->gstart, hipEventDisableTiming));
+            P->gdone.assign(k, nullptr);
+            for (auto& e : P->gdone) MR1L_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         }
     }
     // alias-histogram tiles: every lattice's bins split into ranges of <= 2^18 bins (multiples of
@@ -426,7 +486,8 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     if (sh) {
         bool same = sh->dtype == sp.dtype && sh->L == L;
         for (int l = 0; same && l < L; ++l)
-            same = sh->hdesc[l].M == P->hdesc[l].M && sh->hdesc[l].lgN1 == P->hdesc[l].lgN1;
+            same = sh->hdesc[l].M == P->hdesc[l].M && sh->hdesc[l].lgN == P->hdesc[l].lgN &&
+                   sh->hdesc[l].n3 == P->hdesc[l].n3 && sh->hdesc[l].lgN1 == P->hdesc[l].lgN1;
         if (!same) {
             set_error("share_filters: lattice sizes, four-step splits or dtype differ");
             return MR1L_ERR_ARG;
@@ -577,6 +638,39 @@ static hipError_t inblock_begin(Plan* p, const cx<T>* src, cx<T>* dst, bool forw
     return e;
 }
 
+// The four-step groups of one pass: the first on s, the others round-robin on the plan's group
+// streams, which wait for everything queued on s so far and are waited for by s at the end.  Each
+// group touches only its own lattices' work regions, filters and samples.  With stage timing on,
+// everything stays on s so that the per-stage events bracket single launches.
+struct GroupFork {
+    Plan* p;
+    hipStream_t s;
+    int k = 0;
+    bool on = false;
+    GroupFork(Plan* p_, hipStream_t s_) : p(p_), s(s_) {}
+    hipError_t begin() {
+        on = !p->gstream.empty() && !p->timing;
+        if (!on) return hipSuccess;
+        hipError_t e = hipEventRecord(p->gstart, s);
+        for (size_t i = 0; e == hipSuccess && i < p->gstream.size(); ++i) e = hipStreamWaitEvent(p->gstream[i], p->gstart, 0);
+        return e;
+    }
+    hipStream_t next() {
+        if (!on) return s;
+        const int i = k++;
+        return i == 0 ? s : p->gstream[(i - 1) % p->gstream.size()];
+    }
+    hipError_t end() {
+        if (!on) return hipSuccess;
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; e == hipSuccess && i < p->gstream.size(); ++i) {
+            e = hipEventRecord(p->gdone[i], p->gstream[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p->gdone[i], 0);
+        }
+        return e;
+    }
+};
+
 template <typename T>
 static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
     const bool eval = p->weights == MR1L_W_EVAL;
@@ -592,6 +686,8 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
         a.n_rhs = std::min(p->rhs_chunk, p->n_rhs - r0);
         const cx<T>* yc = y + r0 * a.samp_stride;
         cx<T>* cc = c + r0 * a.n;
+        GroupFork gf(p, s);
+        MR1L_HIP_TRY(gf.begin());
         for (const FftGroup& g : p->sweep) {
             if (g.small) {
                 tm.begin(1);
@@ -600,16 +696,18 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
                 tm.end();
                 continue;
             }
+            const hipStream_t gs = gf.next();
             tm.begin(2);
-            launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, false, s);
+            launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, false, gs);
             tm.end();
             tm.begin(3);
-            launch_p2<T>(a, g, work, filt, -1, yc, nullptr, s);
+            launch_p2<T>(a, g, work, filt, -1, yc, nullptr, gs);
             tm.end();
             tm.begin(4);
-            launch_p3<T>(a, g, work, work, a.work_stride, false, -1, !eval, s);
+            launch_p3<T>(a, g, work, work, a.work_stride, false, -1, !eval, gs);
             tm.end();
         }
+        MR1L_HIP_TRY(gf.end());
         tm.begin(5);
         launch_gather<T>(a, work, cc, eval, s);
         tm.end();
@@ -646,6 +744,8 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
             launch_scatter<T>(a, cc, work, eval, s);
         }
         tm.end();
+        GroupFork gf(p, s);
+        MR1L_HIP_TRY(gf.begin());
         for (const FftGroup& g : p->sweep) {
             if (g.small) {
                 tm.begin(1);
@@ -654,16 +754,18 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
                 tm.end();
                 continue;
             }
+            const hipStream_t gs = gf.next();
             tm.begin(2);
-            launch_p1<T>(a, g, work, a.work_stride, false, work, +1, !eval, s);
+            launch_p1<T>(a, g, work, a.work_stride, false, work, +1, !eval, gs);
             tm.end();
             tm.begin(3);
-            launch_p2<T>(a, g, work, filt, +1, nullptr, yc, s);
+            launch_p2<T>(a, g, work, filt, +1, nullptr, yc, gs);
             tm.end();
             tm.begin(4);
-            launch_p3<T>(a, g, work, yc, a.samp_stride, true, +1, !eval, s);
+            launch_p3<T>(a, g, work, yc, a.samp_stride, true, +1, !eval, gs);
             tm.end();
         }
+        MR1L_HIP_TRY(gf.end());
     }
     if (p->n_inblock > 0) MR1L_HIP_TRY(hipStreamWaitEvent(s, p->join, 0));
     MR1L_HIP_TRY(hipGetLastError());
@@ -826,7 +928,7 @@ mr1l_status mr1l_info(mr1l_plan_t plan, int64_t* sample_offsets, int64_t* n_unco
     }
     if (sample_offsets) std::copy(p->samp_off.begin(), p->samp_off.end(), sample_offsets);
     if (fft_lengths)
-        for (int l = 0; l < p->L; ++l) fft_lengths[l] = (int64_t)1 << p->hdesc[l].lgN;
+        for (int l = 0; l < p->L; ++l) fft_lengths[l] = bl_len(p->hdesc[l]);
     if (n_uncovered) {
         MR1L_HIP_TRY(hipSetDevice(p->device));
         DevMem cnt;

@@ -169,6 +169,11 @@ struct Plan {
     int n_inblock = 0;
     hipStream_t side = nullptr;        // the in-block launch runs here, beside the stage sweep
     hipEvent_t fork = nullptr, join = nullptr;
+    // four-step groups after the first run their stage pipelines (stage 1 -> 2 -> 3) on streams of
+    // their own, from a per-device pool, forked after the index pass and joined before the gather
+    std::vector<hipStream_t> gstream;
+    std::vector<hipEvent_t> gdone;
+    hipEvent_t gstart = nullptr;
     void* filt_ptr = nullptr;          // filt.p, or the filters of the plan shared at creation
     TxArgs args{};
     // plan-cached index work: residues and bitmaps valid from an earlier call

@@ -56,6 +56,15 @@ def batch_inblock(enable: int = -1) -> int:
     return int(out.value)
 
 
+def fft_smooth(mode: int = -1) -> int:
+    """mr1l_fft_smooth: whether plans created from now on may take Bluestein lengths 3 * 2^k
+    (1 where the tuned table says so, 2 wherever the lattices fit, 0 powers of two only, < 0
+    query); returns the mode."""
+    out = C.c_int(0)
+    check(lib().mr1l_fft_smooth(int(mode), C.byref(out)), "mr1l_fft_smooth")
+    return int(out.value)
+
+
 class Plan:
     """mr1l_plan: frequency set I (int [n, d]), lattices (M [L], z [L, d])."""
 

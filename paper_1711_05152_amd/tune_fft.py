@@ -10,8 +10,11 @@ variant exists only where it changes the kernel.  For each precision and length 
 builds a synthetic plan whose lattices all have that length (distinct primes M with 2M - 1 in
 (2^(lgN-1), 2^lgN], about 2^22 Bluestein points in total), times forward + adjoint under every
 (split, variant) (mr1l_fft_split, mr1l_fft_p2_variant), and keeps the fastest when it beats the
-rule's split with variant 0 by more than ``--margin``.  It writes the table, prints one JSON line
-per length and, with ``--report``, a Markdown summary.  Run it on the GPU, then rebuild the library
+rule's split with variant 0 by more than ``--margin``.  Where the class 2^lgN also has a factor-3
+length 3 * 2^(lgN - 2) (lgN - 2 in 12 .. 22), a second synthetic plan with lattices that all fit it
+(M in [2^(lgN-2) + 1, 3 * 2^(lgN-3)]) is timed with the chosen power-of-two schedule and with the
+factor-3 length (mr1l_fft_smooth), which the class then takes when it is faster by the margin.  It
+writes the tables, prints one JSON line per length and, with ``--report``, a Markdown summary.  Run it on the GPU, then rebuild the library
 (``__graft_entry__.build()``): plans read the table when they are created.
 
     python -m paper_1711_05152_amd.tune_fft [--lengths 13-24] [--dtypes c64,c128] [--report FILE]
@@ -103,6 +106,24 @@ def workload(lgn: int, rng: np.random.Generator):
     return freqs, M, z
 
 
+def workload3(lgn: int, rng: np.random.Generator):
+    """Lattices that all fit the factor-3 length 3 * 2^(lgn-2) of the class 2^lgn:
+    M in [2^(lgn-2) + 1, 3 * 2^(lgn-3)], about 2^22 power-of-two points as in ``workload``."""
+    L = max(1, min(64, 1 << max(0, 22 - lgn)))
+    lo, hi = (1 << (lgn - 2)) + 1, 3 << (lgn - 3)
+    M = _primes_in(lo, hi, L, rng)
+    n = int(min(M.min() // 2, 1 << 16))
+    d = 4
+    freqs = np.unique(rng.integers(-1000, 1001, size=(2 * n, d)), axis=0)[:n].astype(np.int32)
+    z = np.stack([rng.integers(0, m, size=d) for m in M]).astype(np.int64)
+    return freqs, M, z
+
+
+def set_smooth(mode: int) -> int:
+    from .mr1l import fft_smooth
+    return fft_smooth(mode)
+
+
 def time_split(freqs, M, z, dtype: str, reps: int) -> float:
     import torch
     from .mr1l import Plan
@@ -146,7 +167,7 @@ def set_p2_variant(dtype: str, lgn: int, v: int) -> int:
     return cur.value
 
 
-def write_table(chosen: dict, chosen_p2: dict, path: str = TABLE) -> None:
+def write_table(chosen: dict, chosen_p2: dict, chosen3: dict = None, path: str = TABLE) -> None:
     def rows(tab):
         out = []
         for dt in ("c64", "c128"):
@@ -160,7 +181,10 @@ def write_table(chosen: dict, chosen_p2: dict, path: str = TABLE) -> None:
            "// Stage-2 variants (bit 0: radix schedule of orders 3 / 2; bit 1: 4096-element row tiles; bit 2:\n"
            "// 8 values per thread) chosen by the same tuner: kTunedP2[dtype][lgN] for the split of kTunedSplit;\n"
            "// -1 keeps variant 0.\n"
-           "static const int8_t kTunedP2[2][25] = {\n" + rows(chosen_p2) + "\n};\n")
+           "static const int8_t kTunedP2[2][25] = {\n" + rows(chosen_p2) + "\n};\n"
+           "// Bluestein length classes 2^lg whose lattices take 3 * 2^(lg - 2) when all of them fit, chosen by\n"
+           "// the same tuner (1: the factor-3 length measured faster; 0 or -1: powers of two).\n"
+           "static const int8_t kTunedSmooth[2][25] = {\n" + rows(chosen3 or {}) + "\n};\n")
     with open(path, "w") as fh:
         fh.write(src)
 
@@ -185,11 +209,13 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
-    chosen, chosen_p2, results = {}, {}, []
+    chosen, chosen_p2, chosen3, results = {}, {}, {}, []
     rng = np.random.default_rng(1711051524)
+    prev_smooth = set_smooth(-1)
     for dtype in args.dtypes.split(","):
         for lgn in parse_lengths(args.lengths):
             freqs, M, z = workload(lgn, rng)
+            set_smooth(0)
             ms = {}
             for s in candidates(lgn):
                 set_split(dtype, lgn, s)
@@ -209,10 +235,28 @@ def main(argv=None) -> int:
                    "ms_fwd_adj": {describe(lgn, *k): round(v, 5) for k, v in ms.items()},
                    "rule": describe(lgn, *r), "chosen": describe(lgn, *pick),
                    "gain_vs_rule": round(1.0 - ms[pick] / ms[r], 4)}
+            if 12 <= lgn - 2 <= 22:
+                # factor-3 length of the class against the power-of-two schedule just chosen
+                f3, M3, z3 = workload3(lgn, rng)
+                set_split(dtype, lgn, pick[0])
+                set_p2_variant(dtype, lgn, pick[1])
+                set_smooth(0)
+                t_pow2 = time_split(f3, M3, z3, dtype, args.reps)
+                set_smooth(2)
+                t_3 = time_split(f3, M3, z3, dtype, args.reps)
+                set_smooth(0)
+                set_p2_variant(dtype, lgn, -2)
+                set_split(dtype, lgn, -1)
+                use3 = t_3 < (1.0 - args.margin) * t_pow2
+                if use3:
+                    chosen3[(dtype, lgn)] = 1
+                row["factor3"] = {"M_range": [int(M3.min()), int(M3.max())], "ms_pow2": round(t_pow2, 5),
+                                  "ms_3x": round(t_3, 5), "chosen": "3x2^%d" % (lgn - 2) if use3 else "2^%d" % lgn}
             results.append(row)
             print(json.dumps(row), flush=True)
+    set_smooth(prev_smooth)
     if not args.no_write:
-        write_table(chosen, chosen_p2, args.table)
+        write_table(chosen, chosen_p2, chosen3, args.table)
     if args.report:
         lines = ["# Four-step split autotuning (Bluestein FFT of the multiple rank-1 lattice transform)", "",
                  "Command (from the repository root on one MI355X):", "", "```",
@@ -230,6 +274,15 @@ def main(argv=None) -> int:
             cells = ", ".join(f"{k}: {v:.4f}" for k, v in r["ms_fwd_adj"].items())
             lines.append(f"| {r['dtype']} | {r['lgN']} | {r['L']} | {cells} | {r['rule']} | {r['chosen']} | "
                          f"{100 * r['gain_vs_rule']:.1f} % |")
+        lines += ["", "Factor-3 lengths: a plan whose lattices all fit 3 * 2^(lgN-2) (sizes below), forward + "
+                  "adjoint in ms with the chosen power-of-two schedule and with the factor-3 length; the class "
+                  "takes the factor-3 length when it is at least %.0f %% faster." % (100 * args.margin), "",
+                  "| dtype | lgN | M range | 2^lgN | 3 * 2^(lgN-2) | chosen |", "|---|---:|---|---:|---:|---|"]
+        for r in results:
+            f = r.get("factor3")
+            if f:
+                lines.append(f"| {r['dtype']} | {r['lgN']} | {f['M_range'][0]} .. {f['M_range'][1]} | "
+                             f"{f['ms_pow2']:.4f} | {f['ms_3x']:.4f} | {f['chosen']} |")
         with open(args.report, "w") as fh:
             fh.write("\n".join(lines) + "\n")
     return 0

@@ -28,6 +28,19 @@ def _to(torch, a, dtype):
                                                                    "c128": torch.complex128}[dtype])
 
 
+class _pow2_only:
+    """Plans created inside take power-of-two Bluestein lengths only (mr1l_fft_smooth(0))."""
+
+    def __enter__(self):
+        from paper_1711_05152_amd.mr1l import fft_smooth
+        self.prev = fft_smooth(-1)
+        fft_smooth(0)
+
+    def __exit__(self, *exc):
+        from paper_1711_05152_amd.mr1l import fft_smooth
+        fft_smooth(self.prev)
+
+
 CASES = [
     # name, n, d, box, L, mlo, mhi, n_rhs
     ("tiny_small_path", 30, 3, 5, 3, 17, 60, 1),
@@ -324,7 +337,9 @@ def test_large_bluestein_lengths(case, dtype):
     name, n, d, box, L, mlo, mhi = case
     p = transform_problem(rng_for(303, zlib.crc32(name.encode())), n, d, box, L, mlo, mhi, n_rhs=2)
     print(f"large {name} {dtype} M={list(p.M)}", flush=True)
-    plan = _plan(p, dtype)
+    with _pow2_only():
+        plan = _plan(p, dtype)
+    assert all(int(v) & (int(v) - 1) == 0 for v in plan.fft_lengths)
     c = plan.forward(_to(torch, p.samples, dtype))
     yy = plan.adjoint(_to(torch, p.coeffs, dtype))
     torch.cuda.synchronize()
@@ -351,6 +366,8 @@ def test_every_compiled_split_matches_oracle(lgn, dtype):
     ref_y = O.adjoint(p.freqs, p.M, p.z, p.coeffs, "paper")
     dt = {"c64": _lib.C64, "c128": _lib.C128}[dtype]
     cur = ctypes.c_int(0)
+    pow2 = _pow2_only()
+    pow2.__enter__()
     try:
         for s in candidates(lgn):
             _lib.check(_lib.lib().mr1l_fft_split(dt, lgn, s, ctypes.byref(cur)), "mr1l_fft_split")
@@ -375,6 +392,66 @@ def test_every_compiled_split_matches_oracle(lgn, dtype):
     finally:
         _lib.lib().mr1l_fft_p2_variant(dt, lgn, -2, None)
         _lib.lib().mr1l_fft_split(dt, lgn, -1, None)
+        pow2.__exit__()
+
+
+def test_smooth_length_class_rule():
+    """A power-of-two length class turns into 3 * 2^k only when all of the plan's lattices in it fit:
+    sizes 5000 and 7000 share the class 2^14 (3 * 2^12 = 12288 covers 2 * 5000 - 1 but not
+    2 * 7000 - 1), so both keep 2^14; 3000 (class 2^13, too short for a factor-3 length) keeps 2^13;
+    sizes 20000 and 21000 (class 2^16, both within 3 * 2^14) both take 49152."""
+    require_gpu()
+    from paper_1711_05152_amd.mr1l import Plan, fft_smooth
+    prev = fft_smooth(-1)
+    fft_smooth(2)
+    rng = np.random.default_rng(7)
+    M = np.array([5003, 7001, 3001, 20011, 21001], np.int64)
+    freqs = rng.integers(-20, 21, size=(300, 3)).astype(np.int32)
+    freqs = np.unique(freqs, axis=0)
+    z = np.stack([rng.integers(0, m, size=3) for m in M]).astype(np.int64)
+    try:
+        plan = Plan(freqs, M, z, dtype="c64", weights="paper", n_rhs=1, device=0)
+        assert [int(v) for v in plan.fft_lengths] == [1 << 14, 1 << 14, 1 << 13, 3 << 14, 3 << 14]
+    finally:
+        fft_smooth(prev)
+
+
+SMOOTH_CASES = [(g, dt, w) for g in range(12, 23) for dt in ("c64", "c128")
+                for w in (("paper", "eval") if g in (14, 18) else ("paper",))]
+
+
+@pytest.mark.parametrize("g,dtype,weights", SMOOTH_CASES, ids=[f"3x2p{g}_{dt}_{w}" for g, dt, w in SMOOTH_CASES])
+def test_smooth_lengths_match_oracle(g, dtype, weights):
+    """Bluestein lengths N = 3 * 2^g for g = 12 .. 22 (lattice sizes M in [2^g + 1, 1.5 * 2^g], so
+    2^(g+1) < 2M - 1 <= 3 * 2^g): with every class allowed (mode 2) the plan takes that length for
+    every lattice, its forward and
+    adjoint agree with the oracle on two right-hand sides (unaligned lattice offsets, so stages 1
+    to 3 run with their column rotation), and a power-of-two plan of the same problem agrees with
+    it to rounding."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import fft_smooth
+    lo, hi = (1 << g) + 1, 3 << (g - 1)
+    L = 2 if g <= 20 else 1
+    p = transform_problem(rng_for(305, g), 1200, 5, 30, L, lo, hi, n_rhs=2)
+    print(f"smooth 3*2^{g} {dtype} {weights} M={list(p.M)}", flush=True)
+    prev = fft_smooth(-1)
+    fft_smooth(2)
+    try:
+        plan = _plan(p, dtype, weights)
+    finally:
+        fft_smooth(prev)
+    assert [int(v) for v in plan.fft_lengths] == [3 << g] * L
+    x, c = _to(torch, p.samples, dtype), _to(torch, p.coeffs, dtype)
+    got_c = plan.forward(x).cpu().numpy()
+    got_y = plan.adjoint(c).cpu().numpy()
+    assert_close(got_c, O.forward(p.freqs, p.M, p.z, p.samples, weights), dtype, f"forward 3*2^{g}")
+    assert_close(got_y, O.adjoint(p.freqs, p.M, p.z, p.coeffs, weights), dtype, f"adjoint 3*2^{g}")
+    del plan
+    with _pow2_only():
+        plan2 = _plan(p, dtype, weights)
+    assert [int(v) for v in plan2.fft_lengths] == [4 << g] * L
+    assert_close(got_c, plan2.forward(x).cpu().numpy().astype(np.complex128), dtype, "3*2^g against 2^(g+2)")
+    assert_close(got_y, plan2.adjoint(c).cpu().numpy().astype(np.complex128), dtype, "3*2^g against 2^(g+2)")
 
 
 def test_graft_smoke_entry_point():
