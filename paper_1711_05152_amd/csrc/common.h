@@ -123,7 +123,7 @@ __host__ __device__ constexpr bool split_compiled(int lgN, int lgN1) {
 int fft_split(int dtype, int lgN);   // split plans of this dtype use for Bluestein length 2^lgN
 
 // Bluestein lengths N = 3 * 2^lgN (lgN in [kMinLg3, kMaxLg3]) take the place of 2^(lgN + 2) for the
-// lattices of a plan in that class when all of them have 2M - 1 <= N: 25 % fewer points.  Their split
+// lattices of a transform in that class when all of them have 2M - 1 <= N: 25 % fewer points.  Their split
 // puts the factor 3 into the stage-2 rows, N = 2^lgN1 * 3 * 2^(lgN - lgN1), with one compiled
 // split per length: rows of at most 3 * 2^11 points and at least 16 columns per stage-1/3 tile.
 constexpr int kMinLg3 = 12, kMaxLg3 = 22;

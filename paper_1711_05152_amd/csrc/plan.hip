@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <tuple>
@@ -19,6 +20,11 @@ void clear_error() { g_err.clear(); }
 
 static const char* kStageNames[MR1L_NSTAGES] = {"alias_hist", "bluestein_small", "bluestein_p1", "bluestein_p2",
                                                 "bluestein_p3", "gather",        "scatter",      "inblock_small"};
+
+// Group streams from this many Bluestein points on: the 512-transform batch (about 2^30 points)
+// gains 2 % from them, while its transforms planned one by one (up to 2^24 points each) lose 8 %
+// to the fork and join of every call.
+constexpr int64_t kGroupStreamMinPoints = (int64_t)1 << 25;
 
 // Streams for the concurrent group pipelines, kept per device between plans (plans of the sparse
 // FFT come and go at every step; creating streams each time would cost more than the transforms).
@@ -63,6 +69,7 @@ Plan::~Plan() {
     if (!gstream.empty()) give_group_streams(device, gstream);
     for (auto e : gdone) hipEventDestroy(e);
     if (gstart) hipEventDestroy(gstart);
+
     for (auto& r : pending) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -289,14 +296,17 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     P->samp_off.assign(L + 1, 0);
     int64_t woff = 0, bmoff = 0;
     std::map<int, std::vector<int>> by_len;   // Bluestein length (2 lgN + n3) -> lattices
-    // A power-of-two class 2^lg turns into 3 * 2^(lg - 2) only when every lattice of the plan in it
-    // fits (2M - 1 <= 3 * 2^(lg - 2)): a class split over two lengths runs twice the launches, each
-    // with half the tiles, which costs more on the GPU than the 25 % fewer points save.
-    bool n3_class[kMaxLgN + 3];
-    for (int lg = 0; lg < kMaxLgN + 3; ++lg) n3_class[lg] = fft_smooth_class(sp.dtype, lg);
+    // A power-of-two class 2^lg turns into 3 * 2^(lg - 2) only when every lattice of the transform in
+    // it fits (2M - 1 <= 3 * 2^(lg - 2)): a class split over two lengths runs twice the launches,
+    // each with half the tiles, which costs more on the GPU than the 25 % fewer points save.  The
+    // choice is per transform, so that a transform of a batched plan gets the bits of its own plan.
+    std::vector<int> lat_tx(L);
+    for (int i = 0, l = 0; i < ntx; ++i)
+        for (int k = 0; k < sp.tx_L[i]; ++k) lat_tx[l++] = i;
+    std::set<std::pair<int, int>> no3;   // (transform, class) with a lattice above 3 * 2^(lg - 2)
     for (int l = 0; l < L; ++l) {
         const int lg = ceil_lg(2 * sp.M[l] - 1);
-        if (lg - 2 >= kMinLg3 && lg - 2 <= kMaxLg3 && (3LL << (lg - 2)) < 2 * sp.M[l] - 1) n3_class[lg] = false;
+        if (lg - 2 >= kMinLg3 && lg - 2 <= kMaxLg3 && (3LL << (lg - 2)) < 2 * sp.M[l] - 1) no3.insert({lat_tx[l], lg});
     }
     for (int l = 0; l < L; ++l) {
         LatDesc& D = P->hdesc[l];
@@ -306,7 +316,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->samp_off[l + 1] = P->samp_off[l] + D.M;
         D.lgN = ceil_lg(2 * D.M - 1);
         D.n3 = 0;
-        if (n3_class[D.lgN]) {
+        if (fft_smooth_class(sp.dtype, D.lgN) && !no3.count({lat_tx[l], D.lgN})) {
             D.lgN -= 2;   // N = 3 * 2^(lgN - 2) < 2^lgN still covers 2M - 1
             D.n3 = 1;
         }
@@ -412,9 +422,13 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
                 P->sweep.push_back(g);
             }
         }
+        // only where the groups carry enough work (kGroupStreamMinPoints)
         int n4 = 0;
+        int64_t pts = 0;
         for (const FftGroup& g : P->sweep) n4 += !g.small;
-        if (n4 >= 2) {
+        for (int l = 0; l < L; ++l)
+            if (!P->hdesc[l].small && !P->htx[P->hdesc[l].tx].in_block) pts += bl_len(P->hdesc[l]);
+        if (n4 >= 2 && pts * sp.n_rhs >= kGroupStreamMinPoints) {
             const int k = std::min(n4 - 1, kGroupStreams);
             MR1L_HIP_TRY(take_group_streams(P->device, k, P->gstream));
             MR1L_HIP_TRY(hipEventCreateWithFlags(&P->gstart, hipEventDisableTiming));
