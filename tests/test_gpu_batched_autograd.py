@@ -104,6 +104,48 @@ def test_batched_graph_replay():
         del junk
 
 
+def test_batched_group_streams_graph_replay():
+    """A batch large enough (over 2^25 Bluestein points, three length groups) that the groups' stage
+    pipelines run on concurrent streams: forward and adjoint equal the transforms' own plans bit for
+    bit, and graph replays (with eager work and synchronisation between them) equal the eager call."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import BatchedPlan, Plan
+    rng = rng_for(506)
+    probs = [transform_problem(rng, 1 << 15, 6, 40, 12, lo, 2 * lo, with_data=False)
+             for lo in (1 << 17, 1 << 18, 1 << 19)]
+    bp = BatchedPlan([(p.freqs, p.M, p.z) for p in probs], dtype="c64", device=0)
+    assert sum(int(v) for v in bp.fft_lengths) >= 1 << 25
+    g = torch.Generator(device="cuda:0").manual_seed(506)
+    y = torch.randn((1, bp.sum_M), dtype=torch.complex64, device="cuda:0", generator=g)
+    c = torch.randn((1, bp.n), dtype=torch.complex64, device="cuda:0", generator=g)
+    ref_c = bp.forward(y).clone()
+    ref_y = bp.adjoint(c).clone()
+    fo = bp.freq_offsets
+    so = np.concatenate([[0], np.cumsum([int(p.M.sum()) for p in probs])])
+    for b, p in enumerate(probs):
+        pp = Plan(p.freqs, p.M, p.z, dtype="c64", device=0)
+        assert torch.equal(torch.view_as_real(pp.forward(y[:, so[b]:so[b + 1]].contiguous())),
+                           torch.view_as_real(ref_c[:, fo[b]:fo[b + 1]])), b
+        assert torch.equal(torch.view_as_real(pp.adjoint(c[:, fo[b]:fo[b + 1]].contiguous())),
+                           torch.view_as_real(ref_y[:, so[b]:so[b + 1]])), b
+        pp.close()
+    c_out = bp.empty_coeffs()
+    y_out = bp.empty_samples()
+    gf = bp.capture("forward", y, c_out)
+    ga = bp.capture("adjoint", c, y_out)
+    for rep in range(3):
+        c_out.zero_()
+        y_out.zero_()
+        junk = bp.forward(y) * 2 + 1            # eager work between replays
+        torch.cuda.synchronize()
+        gf.replay()
+        ga.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.view_as_real(c_out), torch.view_as_real(ref_c)), rep
+        assert torch.equal(torch.view_as_real(y_out), torch.view_as_real(ref_y)), rep
+        del junk
+
+
 def test_autograd_gradcheck_double():
     torch = require_gpu()
     from paper_1711_05152_amd.mr1l import Plan
