@@ -146,9 +146,10 @@ void filter_cache_clear(int dev) {
 }
 
 // copy every lattice's spectrum from the cache, or (any missing) build them all and remember the
-// missing ones; on the null stream, like the rest of plan creation
+// missing ones; on the stream of the plan's set-up.  New cache entries are complete before this
+// returns (plans on other streams may copy from them at once).
 template <typename T>
-static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
+static hipError_t plan_filters(Plan* P, const TxArgs& a, int device, hipStream_t st) {
     const int L = P->L;
     cx<T>* filt = (cx<T>*)P->filt_ptr;
     std::vector<int> miss;
@@ -169,10 +170,10 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
                 segs.push_back(CopySeg{h.first->buf.p, filt + D.filt_off, (uint64_t)bl_len(D) * sizeof(cx<T>)});
                 const_cast<FiltEntry*>(h.first)->used = ++g_fc_clock;
             }
-            return copy_segments(segs.data(), (int)segs.size(), nullptr);
+            return copy_segments(segs.data(), (int)segs.size(), st);
         }
     }
-    hipError_t e = build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, filt, device, nullptr);
+    hipError_t e = build_filters<T>(P->hdesc.data(), L, a.desc, P->groups, filt, device, st);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(fc_mutex());
     auto& m = fc_map();
@@ -186,7 +187,7 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
             (void)hipGetLastError();
             break;   // no room: the cache is an optimisation only
         }
-        e = hipMemcpyAsync(ent.buf.p, filt + D.filt_off, bytes, hipMemcpyDeviceToDevice, nullptr);
+        e = hipMemcpyAsync(ent.buf.p, filt + D.filt_off, bytes, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
         ent.used = ++g_fc_clock;
         g_fc_bytes += bytes;
@@ -199,7 +200,8 @@ static hipError_t plan_filters(Plan* P, const TxArgs& a, int device) {
             m.erase(old);
         }
     }
-    return hipSuccess;
+    // the entries' copies are queued on st: done before another stream may read them
+    return miss.empty() ? hipSuccess : hipStreamSynchronize(st);
 }
 
 template <typename T>
@@ -524,7 +526,7 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     if (P->args.bsort) {
         const int64_t nchunks = (P->sum_M + kScanChunk - 1) / kScanChunk;
         MR1L_HIP_TRY(P->bcnt.alloc((size_t)P->sum_M * sizeof(int32_t)));
-        MR1L_HIP_TRY(hipMemsetAsync(P->bcnt.p, 0, (size_t)P->sum_M * sizeof(int32_t), nullptr));
+        MR1L_HIP_TRY(hipMemsetAsync(P->bcnt.p, 0, (size_t)P->sum_M * sizeof(int32_t), sp.stream));
         MR1L_HIP_TRY(P->bloc.alloc((size_t)P->sum_M * sizeof(int32_t)));
         MR1L_HIP_TRY(P->bbase.alloc((size_t)std::max<int64_t>(1, nchunks) * sizeof(int32_t)));
         MR1L_HIP_TRY(P->perm.alloc((size_t)std::max<int64_t>(4, (int64_t)max_nlat * rstride) * sizeof(int32_t)));
@@ -564,14 +566,14 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     // lattice descriptors as complete (fused-pass tiles included), then every staged table
     MR1L_HIP_TRY(stg.add(P->desc, P->hdesc.data(), P->hdesc.size() * sizeof(LatDesc)));
     a.desc = P->desc.as<LatDesc>();
-    MR1L_HIP_TRY(stg.flush(nullptr));
+    MR1L_HIP_TRY(stg.flush(sp.stream));
     if (!twiddles<T>(sp.device) || !twiddles<double>(sp.device)) {
         set_error("could not allocate twiddle tables");
         return MR1L_ERR_NOMEM;
     }
-    if (!sh) MR1L_HIP_TRY(plan_filters<T>(P, a, sp.device));
+    if (!sh) MR1L_HIP_TRY(plan_filters<T>(P, a, sp.device, sp.stream));
     MR1L_HIP_TRY(hipGetLastError());
-    MR1L_HIP_TRY(hipDeviceSynchronize());
+    if (sp.sync) MR1L_HIP_TRY(hipDeviceSynchronize());
     *out = guard.release();
     return MR1L_OK;
 }

@@ -137,6 +137,11 @@ struct PlanSpec {
     int64_t max_work_bytes = work_limit_bytes();   // bound of the Bluestein work area (rhs chunking)
     // reuse the filter spectra of a plan with the same lattice sizes (same order) and dtype
     const struct Plan* share_filters = nullptr;
+    // set-up work (table copies, filter spectra) goes to ``stream``; with sync the device is
+    // synchronised before plan_create returns (the public entry points), without it the plan may
+    // only be used on ``stream`` (the sparse-FFT driver's own plans)
+    hipStream_t stream = nullptr;
+    bool sync = true;
     // transforms
     std::vector<int64_t> tx_n;         // frequencies per transform
     std::vector<int32_t> tx_L;         // lattices per transform

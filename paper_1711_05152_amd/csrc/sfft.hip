@@ -273,8 +273,8 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
         sp.tx_L = {L};
         sp.M = cr.M;
         sp.z = cr.z;
-        PlanGuard pJ;
-        TRY(plan_create(sp, &pJ.p));
+        sp.stream = C.st;   // set up on the driver's stream, without a device-wide wait
+        sp.sync = false;
         if (C.stats) {
             C.stats->L[t - 1] = L;
             C.stats->sumM[t - 1] = sumM;
@@ -301,6 +301,10 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
             MR1L_HIP_TRY(stg.flush(C.st));
         }
         MR1L_HIP_TRY(y.alloc((size_t)rt * std::max<int64_t>(1, sumM) * csz));
+        // the sampling plan (built-in black box) is created first, with the lattices' filter
+        // spectra; the transform plan shares them and is set up while the device samples, so it
+        // must not outlive the sampling plan (declared before it)
+        PlanGuard pP;
         if (C.planted) {
             if (C.s_pl > 0) {
                 PlanSpec pp;
@@ -313,12 +317,12 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
                 pp.dev_ktype = K_I32;
                 pp.dev_maxabs = C.pl_maxabs;
                 pp.check_distinct = false;
-                pp.share_filters = pJ.p;
                 pp.tx_n = {C.s_pl};
                 pp.tx_L = {L};
                 pp.M = cr.M;
                 pp.z = cr.z;
-                PlanGuard pP;
+                pp.stream = C.st;
+                pp.sync = false;
                 TRY(plan_create(pp, &pP.p));
                 DevMem w;
                 MR1L_HIP_TRY(w.alloc((size_t)rt * C.s_pl * csz));
@@ -326,7 +330,6 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
                 for (int i0 = 0; i0 < rt; i0 += per_call)
                     TRY(plan_adjoint(pP.p, (const char*)w.p + (size_t)i0 * C.s_pl * csz,
                                      (char*)y.p + (size_t)i0 * sumM * csz, C.st));
-                TRY(sync_check(C.st));
             } else {
                 MR1L_HIP_TRY(hipMemsetAsync(y.p, 0, (size_t)rt * sumM * csz, C.st));
             }
@@ -354,9 +357,17 @@ mr1l_status run(Ctx& C, int64_t cap, int64_t* n_out, int32_t* freqs_out, double*
                 }
             }
         }
+        // the transform plan, set up on the host while the device samples; its host time counts
+        // as construction
+        const auto tp = clk::now();
+        sp.share_filters = pP.p;
+        PlanGuard pJ;
+        TRY(plan_create(sp, &pJ.p));
+        const double ms_plan = ms_since(tp);
         TRY(sync_check(C.st));
         if (C.stats) {
-            C.stats->ms_sampling += ms_since(t0);
+            C.stats->ms_construct += ms_plan;
+            C.stats->ms_sampling += ms_since(t0) - ms_plan;
             C.stats->samples += (int64_t)rt * (1 - L + sumM);
             C.stats->samples_full += (int64_t)rt * sumM;
         }
