@@ -427,20 +427,24 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const cx<T>* __restrict_
         if constexpr (LGNS > 0) {
             const int k = j & ((1 << LGNS) - 1);
             const int step = k << (kTwLg - LGNS - LR);
+            // w, w^2, w^4, w^8 from the table and the other powers as products; in double precision
+            // the even powers are squares of w instead (one 16-byte load per butterfly: complex128
+            // standalone step 0.208 -> 0.205 ms; in single precision the loads measured faster)
+            constexpr bool SQ = sizeof(T) == 8;
             cx<T> w[R];
             w[1] = tw[step];
             if constexpr (R >= 4) {
-                w[2] = tw[2 * step];
+                w[2] = SQ ? cmul(w[1], w[1]) : tw[2 * step];
                 w[3] = cmul(w[1], w[2]);
             }
             if constexpr (R >= 8) {
-                w[4] = tw[4 * step];
+                w[4] = SQ ? cmul(w[2], w[2]) : tw[4 * step];
                 w[5] = cmul(w[1], w[4]);
                 w[6] = cmul(w[2], w[4]);
                 w[7] = cmul(w[3], w[4]);
             }
             if constexpr (R >= 16) {
-                w[8] = tw[8 * step];
+                w[8] = SQ ? cmul(w[4], w[4]) : tw[8 * step];
 #pragma unroll
                 for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
             }
