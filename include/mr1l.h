@@ -200,8 +200,10 @@ mr1l_status mr1l_batch_inblock(int enable, int* current);
  * lattices of a transform whose power-of-two length would be 2^(k+2), 2^12 <= 2^k <= 2^22, may
  * take N = 3 * 2^k instead (25 % fewer points) when every one of them fits, 3 * 2^k >= 2M - 1; a
  * class whose lattices do not all fit keeps 2^(k+2) for all of them (two lengths in one class cost
- * more launches than the smaller one saves).  The choice is per transform, so a transform of a
- * batched plan takes the lengths (and gives the bits) of its own plan.  mode 1 (the default) does so for the classes where the
+ * more launches than the smaller one saves), except in a transform of at least 2^25 power-of-two
+ * points times right-hand sides, where every lattice that fits takes 3 * 2^k.  The choice is per
+ * transform, so a transform of a batched plan takes the lengths (and gives the bits) of its own
+ * plan with the same number of right-hand sides.  mode 1 (the default) does so for the classes where the
  * autotuner (paper_1711_05152_amd/tune_fft.py) measured the factor-3 length faster, 2 for every
  * class, 0 never; < 0 only queries.  ``current`` (optional) receives the mode.  Plans read it when
  * they are created; results agree to rounding either way.  Errors: MR1L_ERR_ARG for a mode above 2. */

@@ -123,13 +123,15 @@ __host__ __device__ constexpr bool split_compiled(int lgN, int lgN1) {
 int fft_split(int dtype, int lgN);   // split plans of this dtype use for Bluestein length 2^lgN
 
 // Bluestein lengths N = 3 * 2^lgN (lgN in [kMinLg3, kMaxLg3]) take the place of 2^(lgN + 2) for the
-// lattices of a transform in that class when all of them have 2M - 1 <= N: 25 % fewer points.  Their split
-// puts the factor 3 into the stage-2 rows, N = 2^lgN1 * 3 * 2^(lgN - lgN1), with one compiled
-// split per length: rows of at most 3 * 2^11 points and at least 16 columns per stage-1/3 tile.
+// lattices of a transform in that class when all of them have 2M - 1 <= N (in large transforms:
+// each lattice that does): 25 % fewer points.  Their split puts the factor 3 into the stage-2 rows,
+// N = 2^lgN1 * 3 * 2^(lgN - lgN1), with one compiled split per length: rows of at most 3 * 2^10
+// points (3 * 2^11-point rows left two workgroups per CU in stage 2) and at least 16 columns per
+// stage-1/3 tile where the length allows.
 constexpr int kMinLg3 = 12, kMaxLg3 = 22;
 constexpr int kGroupStreams = 3;   // extra streams of a plan for concurrent Bluestein groups
 __host__ __device__ constexpr int split3_lgN1(int lgN) {
-    return (lgN - 11) > ((lgN + 1) / 2 < 8 ? (lgN + 1) / 2 : 8) ? (lgN - 11) : ((lgN + 1) / 2 < 8 ? (lgN + 1) / 2 : 8);
+    return (lgN - 10) > ((lgN + 1) / 2 < 8 ? (lgN + 1) / 2 : 8) ? (lgN - 10) : ((lgN + 1) / 2 < 8 ? (lgN + 1) / 2 : 8);
 }
 // plans of this dtype created now may turn the power-of-two class 2^lg into 3 * 2^(lg - 2)
 bool fft_smooth_class(int dtype, int lg);

@@ -25,6 +25,7 @@ static const char* kStageNames[MR1L_NSTAGES] = {"alias_hist", "bluestein_small",
 // gains 2 % from them, while its transforms planned one by one (up to 2^24 points each) lose 8 %
 // to the fork and join of every call.
 constexpr int64_t kGroupStreamMinPoints = (int64_t)1 << 25;
+constexpr int64_t kSplitClassMinPoints = kGroupStreamMinPoints;
 
 // Streams for the concurrent group pipelines, kept per device between plans (plans of the sparse
 // FFT come and go at every step; creating streams each time would cost more than the transforms).
@@ -305,9 +306,15 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
     std::vector<int> lat_tx(L);
     for (int i = 0, l = 0; i < ntx; ++i)
         for (int k = 0; k < sp.tx_L[i]; ++k) lat_tx[l++] = i;
+    // A large transform (at least 2^25 power-of-two points times right-hand sides) splits a class:
+    // its launches carry enough tiles that two lengths on two streams cost nothing extra, so every
+    // lattice that fits takes the factor-3 length.
+    std::vector<int64_t> tx_pts(ntx, 0);
+    for (int l = 0; l < L; ++l) tx_pts[lat_tx[l]] += (int64_t)1 << ceil_lg(2 * sp.M[l] - 1);
     std::set<std::pair<int, int>> no3;   // (transform, class) with a lattice above 3 * 2^(lg - 2)
     for (int l = 0; l < L; ++l) {
         const int lg = ceil_lg(2 * sp.M[l] - 1);
+        if (tx_pts[lat_tx[l]] * sp.n_rhs >= kSplitClassMinPoints) continue;
         if (lg - 2 >= kMinLg3 && lg - 2 <= kMaxLg3 && (3LL << (lg - 2)) < 2 * sp.M[l] - 1) no3.insert({lat_tx[l], lg});
     }
     for (int l = 0; l < L; ++l) {
@@ -318,7 +325,8 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->samp_off[l + 1] = P->samp_off[l] + D.M;
         D.lgN = ceil_lg(2 * D.M - 1);
         D.n3 = 0;
-        if (fft_smooth_class(sp.dtype, D.lgN) && !no3.count({lat_tx[l], D.lgN})) {
+        if (fft_smooth_class(sp.dtype, D.lgN) && !no3.count({lat_tx[l], D.lgN}) &&
+            (3LL << (D.lgN - 2)) >= 2 * D.M - 1) {
             D.lgN -= 2;   // N = 3 * 2^(lgN - 2) < 2^lgN still covers 2M - 1
             D.n3 = 1;
         }

@@ -95,10 +95,11 @@ def _primes_in(lo: int, hi: int, count: int, rng: np.random.Generator) -> np.nda
 
 def workload(lgn: int, rng: np.random.Generator):
     """Lattices of Bluestein length exactly 2^lgn: M in [2^(lgn-2) + 1, 2^(lgn-1)] so 2M - 1 lies
-    in (2^(lgn-1), 2^lgn); about 2^22 Bluestein points over at most 64 lattices."""
+    in (2^(lgn-1), 2^lgn), spread over the whole class as primes drawn from an octave are; about
+    2^22 Bluestein points over at most 64 lattices.  (Timed with powers of two only.)"""
     L = max(1, min(64, 1 << max(0, 22 - lgn)))
     lo, hi = (1 << (lgn - 2)) + 1, 1 << (lgn - 1)
-    M = _primes_in(lo + (hi - lo) // 2, hi, L, rng)
+    M = _primes_in(lo, hi, L, rng)
     n = int(min(M.min() // 2, 1 << 16))
     d = 4
     freqs = np.unique(rng.integers(-1000, 1001, size=(2 * n, d)), axis=0)[:n].astype(np.int32)
@@ -201,8 +202,8 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--lengths", default="13-24")
     ap.add_argument("--dtypes", default="c64,c128")
-    ap.add_argument("--reps", type=int, default=10)
-    ap.add_argument("--margin", type=float, default=0.02, help="relative gain needed to leave the rule")
+    ap.add_argument("--reps", type=int, default=30)
+    ap.add_argument("--margin", type=float, default=0.015, help="relative gain needed to leave the rule")
     ap.add_argument("--report", default=None, help="also write a Markdown summary to this file")
     ap.add_argument("--no-write", action="store_true", help="measure only; leave the table alone")
     ap.add_argument("--table", default=TABLE, help="where to write the table (default: the library's source)")

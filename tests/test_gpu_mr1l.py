@@ -416,6 +416,36 @@ def test_smooth_length_class_rule():
         fft_smooth(prev)
 
 
+def test_large_transform_splits_length_class():
+    """A transform of at least 2^25 power-of-two points times right-hand sides splits a class: of the
+    sizes 1200007 (2M - 1 within 3 * 2^20) and 1900009 (not) in the class 2^22, the first takes
+    3 * 2^20 with four right-hand sides (2 x 2^22 x 4 = 2^25) and 2^22 with one; forward and
+    adjoint of the split plan agree with the oracle."""
+    torch = require_gpu()
+    from paper_1711_05152_amd.mr1l import Plan, fft_smooth
+    prev = fft_smooth(-1)
+    fft_smooth(2)
+    from workloads import distinct_freqs
+    rng = rng_for(307)
+    freqs = distinct_freqs(rng, 600, 4, -20, 20)
+    M = np.array([1200007, 1900009], np.int64)
+    z = np.stack([rng.integers(0, m, size=4) for m in M]).astype(np.int64)
+    samples = cn01(rng, (4, int(M.sum())))
+    coeffs = cn01(rng, (4, freqs.shape[0]))
+    try:
+        one = Plan(freqs, M, z, dtype="c64", weights="paper", n_rhs=1, device=0)
+        assert [int(v) for v in one.fft_lengths] == [1 << 22, 1 << 22]
+        one.close()
+        plan = Plan(freqs, M, z, dtype="c64", weights="paper", n_rhs=4, device=0)
+        assert [int(v) for v in plan.fft_lengths] == [3 << 20, 1 << 22]
+    finally:
+        fft_smooth(prev)
+    got_c = plan.forward(_to(torch, samples, "c64")).cpu().numpy()
+    got_y = plan.adjoint(_to(torch, coeffs, "c64")).cpu().numpy()
+    assert_close(got_c, O.forward(freqs, M, z, samples, "paper"), "c64", "forward, split class")
+    assert_close(got_y, O.adjoint(freqs, M, z, coeffs, "paper"), "c64", "adjoint, split class")
+
+
 SMOOTH_CASES = [(g, dt, w) for g in range(12, 23) for dt in ("c64", "c128")
                 for w in (("paper", "eval") if g in (14, 18) else ("paper",))]
 
