@@ -801,7 +801,7 @@ def bluestein_alu(stage: str, ms: float, Ns, dtype: str):
         if N % 3 == 0:
             # N = 3 * 2^lg: one compiled split, the factor 3 in the stage-2 rows
             lg = int(round(math.log2(N // 3)))
-            lg1 = max(lg - 11, min((lg + 1) // 2, 8))
+            lg1 = max(lg - 10, min((lg + 1) // 2, 8))
         else:
             lg = int(round(math.log2(N)))
             cur = C.c_int(0)
