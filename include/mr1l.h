@@ -195,6 +195,20 @@ mr1l_status mr1l_work_limit(int64_t max_bytes, int64_t* current);
  * created.  Never fails. */
 mr1l_status mr1l_batch_inblock(int enable, int* current);
 
+/* Right-hand sides side by side.  With several right-hand sides per pass, the forward's gather
+ * (Alg. 2's average, or the Fourier-matrix weights' sum over the lattices) reads one random bin
+ * per frequency, lattice and right-hand side, and the Fourier-matrix adjoint one random
+ * coefficient per frequency, lattice and right-hand side.  Interleaving copies a block of 8
+ * (complex64) or 4 (complex128) right-hand sides into 64-byte slots first, bins (forward) or
+ * coefficients (adjoint), so that one random read fetches the whole block; the sums keep their
+ * order, so results are the same bits either way.  mode 1 (the default) interleaves where the
+ * pass's random reads leave the caches: bins of at least 256 MB per pass (sum M x right-hand sides
+ * x element size), coefficients of at least 4 MB; 2 interleaves every pass of several right-hand
+ * sides, 0 none; < 0 only queries.  ``current`` (optional) receives the mode.  Plans read it when
+ * they are created and then hold a buffer of max(n, sum M) x 64 bytes (only while that is within
+ * the work-area bound of mr1l_work_limit).  Errors: MR1L_ERR_ARG for a mode above 2. */
+mr1l_status mr1l_rhs_interleave(int mode, int* current);
+
 /* Bluestein lengths with a factor 3.  The convolution length of a lattice of size M must be at
  * least 2M - 1 (the chirp-z form of its prime-length DFT, Alg. 2's one-dimensional DFTs).  The
  * lattices of a transform whose power-of-two length would be 2^(k+2), 2^12 <= 2^k <= 2^22, may

@@ -16,7 +16,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OVERFLOW", 3: "ERR_NOMEM", 4: "ERR_HIP"
           6: "ERR_UNSUPPORTED", 16: "WARN_UNCOVERED"}
 
 EXPORTED = ["mr1l_plan", "mr1l_plan_batched", "mr1l_forward", "mr1l_adjoint", "mr1l_alias", "mr1l_info", "mr1l_destroy",
-            "mr1l_timing_enable", "mr1l_timing_read", "mr1l_cache_alias", "mr1l_memory_cache", "mr1l_fft_split", "mr1l_fft_p2_variant", "mr1l_work_limit", "mr1l_batch_inblock", "mr1l_fft_smooth", "mr1l_lsq_residual", "mr1l_lsq_residual_noalloc", "mr1l_construct", "sfft_detect",
+            "mr1l_timing_enable", "mr1l_timing_read", "mr1l_cache_alias", "mr1l_memory_cache", "mr1l_fft_split", "mr1l_fft_p2_variant", "mr1l_work_limit", "mr1l_batch_inblock", "mr1l_rhs_interleave", "mr1l_fft_smooth", "mr1l_lsq_residual", "mr1l_lsq_residual_noalloc", "mr1l_construct", "sfft_detect",
             "sfft_sample_bspline", "sfft_bspline_coeffs", "sfft_bspline_l2_error", "mr1l_last_error", "mr1l_version"]
 
 
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         "mr1l_fft_p2_variant": [i32, i32, i32, C.POINTER(i32)],
         "mr1l_work_limit": [i64, C.POINTER(i64)],
         "mr1l_batch_inblock": [i32, C.POINTER(i32)],
+        "mr1l_rhs_interleave": [i32, C.POINTER(i32)],
         "mr1l_fft_smooth": [i32, C.POINTER(i32)],
         "mr1l_lsq_residual": [vp, vp, vp, vp, vp, vp, vp],
         "mr1l_lsq_residual_noalloc": [vp, vp, vp, vp, vp, vp, vp],

@@ -237,6 +237,10 @@ struct TxArgs {
     int32_t* perm;            // [max_nlat][rs]
     int64_t nbins;            // sum_M
     int64_t max_M;            // largest lattice size
+    // right-hand-side interleaving buffer of max(n, sum_M) 64-byte slots (null: not used), and
+    // whether the gather (bins) and the bin sums (coefficients) go through it
+    void* ilv;
+    bool ilv_bins, ilv_coef;
     bool fast_mod;            // residues may use the fp64 quotient estimate
     // 32-bit residue path: |k . z| < 2^31 for every frequency and lattice, |k_c| < 2^23 and d <= 32;
     // z32 holds the reduced generators as int32 rows padded with zeros
@@ -245,6 +249,12 @@ struct TxArgs {
     int zrow;                 // row stride of z32 (16 or 32)
     const int32_t* z32;
 };
+
+// Interleaving a pass's right-hand sides pays where its random reads leave the caches: the
+// gather's bins beyond the 256 MB Infinity Cache (inside it the copy costs more than the reads it
+// saves), the bin sums' coefficients beyond a 4 MB L2.
+constexpr int64_t kIlvBinBytes = (int64_t)1 << 28;
+constexpr int64_t kIlvCoefBytes = (int64_t)1 << 22;
 
 template <typename T> const cx<T>* twiddles(int device);   // e^{-2 pi i m/4096}, m < 4096
 

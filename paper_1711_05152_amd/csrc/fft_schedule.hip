@@ -28,6 +28,7 @@ constexpr int64_t kDefaultWorkLimit = (int64_t)4 << 30;
 std::atomic<int64_t> g_work_limit{kDefaultWorkLimit};
 std::atomic<int> g_inblock{1};
 std::atomic<int> g_smooth{1};
+std::atomic<int> g_interleave{1};
 
 int table_split(int dt, int lgN) {
     const int t = kTunedSplit[dt][lgN];
@@ -52,6 +53,7 @@ int fft_p2_variant(int dtype, int lgN, int lg1) {
 
 int64_t work_limit_bytes() { return g_work_limit.load(); }
 bool batch_inblock_enabled() { return g_inblock.load() != 0; }
+int rhs_interleave_mode() { return g_interleave.load(); }
 bool fft_smooth_class(int dtype, int lg) {
     const int m = g_smooth.load();
     if (lg < kMinLg3 + 2 || lg > kMaxLg3 + 2) return false;
@@ -74,6 +76,17 @@ extern "C" mr1l_status mr1l_batch_inblock(int enable, int* current) {
     clear_error();
     if (enable >= 0) g_inblock.store(enable ? 1 : 0);
     if (current) *current = g_inblock.load();
+    return MR1L_OK;
+}
+
+extern "C" mr1l_status mr1l_rhs_interleave(int mode, int* current) {
+    clear_error();
+    if (mode > 2) {
+        set_error("mr1l_rhs_interleave: mode 0 (never), 1 (by size) or 2 (every pass of several right-hand sides)");
+        return MR1L_ERR_ARG;
+    }
+    if (mode >= 0) g_interleave.store(mode);
+    if (current) *current = g_interleave.load();
     return MR1L_OK;
 }
 

@@ -14,6 +14,7 @@
 #include "index_dev.h"
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 namespace mr1l {
@@ -536,9 +537,10 @@ __global__ __launch_bounds__(256) void k_scatter(TxArgs a, const cx<T>* __restri
 
 // ---- Fourier-matrix adjoint by counting sort --------------------------------------------------------
 // bins_l[m] = sum over k with r_l(k) = m of c_k (synthesis A c on the lattices, Sec. 2.1): the pairs
-// (k, l) are counted per bin, the counts scanned, the pairs placed in bin order, and one thread per
-// bin adds its frequencies' coefficients in ascending k (sorted when the bin holds <= kBinSort of
-// them), so every bin is written exactly once and the result does not depend on scheduling.
+// (k, l) are counted per bin, the counts scanned, the pairs placed in bin order, each bin's list put
+// in ascending k (when the bin holds <= kBinSort of them; once per sort, not per right-hand-side
+// chunk), and one thread per bin adds its frequencies' coefficients in list order, so every bin is
+// written exactly once and the result does not depend on scheduling.
 constexpr int kBinSort = 16;
 
 template <bool SINGLE>
@@ -625,8 +627,58 @@ __global__ __launch_bounds__(256) void k_bin_place(TxArgs a) {
     }
 }
 
-// one thread per bin m of lattice blockIdx.y, every right-hand side of the chunk
-template <typename T>
+// list of bin m (one thread per bin of lattice blockIdx.y) in ascending k: bins of up to four
+// frequencies (almost all of them when the bins outnumber the frequencies) by a sorting network in
+// registers, up to kBinSort by insertion, larger ones stay in placement order
+__global__ __launch_bounds__(256) void k_bin_order(TxArgs a) {
+    const int l = blockIdx.y;
+    const LatDesc D = a.desc[l];
+    const TxDesc t = a.tx[D.tx];
+    const int j = l - t.lat0;
+    const int base = bin_offset(a, D.samp_off);
+    int32_t* pm = a.perm + (int64_t)j * a.rs + t.foff;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < D.M; m += (int64_t)gridDim.x * blockDim.x) {
+        const int beg = bin_offset(a, D.samp_off + m) - base;
+        const int end = m + 1 < D.M ? bin_offset(a, D.samp_off + m + 1) - base : (int)t.fn;
+        const int cnt = end - beg;
+        if (cnt <= 1 || cnt > kBinSort) continue;
+        if (cnt <= 4) {
+            int x[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[i] = i < cnt ? pm[beg + i] : INT_MAX;
+            auto cx2 = [](int& u, int& v) {
+                const int lo = min(u, v), hi = max(u, v);
+                u = lo;
+                v = hi;
+            };
+            cx2(x[0], x[1]);
+            cx2(x[2], x[3]);
+            cx2(x[0], x[2]);
+            cx2(x[1], x[3]);
+            cx2(x[1], x[2]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < cnt) pm[beg + i] = x[i];
+            continue;
+        }
+        int ks[kBinSort];
+        for (int i = 0; i < cnt; ++i) {   // insertion sort: ascending k
+            const int k = pm[beg + i];
+            int q = i;
+            while (q > 0 && ks[q - 1] > k) {
+                ks[q] = ks[q - 1];
+                --q;
+            }
+            ks[q] = k;
+        }
+        for (int i = 0; i < cnt; ++i) pm[beg + i] = ks[i];
+    }
+}
+
+// one thread per bin m of lattice blockIdx.y, every right-hand side of the chunk, RB of them at a
+// time: the RB coefficient loads of one frequency are independent, so they are in flight together
+// (each right-hand side adds the bin's frequencies in list order)
+template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_bin_sum(TxArgs a, const cx<T>* __restrict__ coeffs, cx<T>* work) {
     const int l = blockIdx.y;
     const LatDesc D = a.desc[l];
@@ -638,28 +690,162 @@ __global__ __launch_bounds__(256) void k_bin_sum(TxArgs a, const cx<T>* __restri
         const int beg = bin_offset(a, D.samp_off + m) - base;
         const int end = m + 1 < D.M ? bin_offset(a, D.samp_off + m + 1) - base : (int)t.fn;
         const int cnt = end - beg;
-        int ks[kBinSort];
-        if (cnt <= kBinSort) {
-            for (int i = 0; i < cnt; ++i) {   // insertion sort: ascending k
-                const int k = pm[beg + i];
-                int q = i;
-                while (q > 0 && ks[q - 1] > k) {
-                    ks[q] = ks[q - 1];
-                    --q;
+        constexpr int KH = 2;   // leading frequencies of the list held in registers
+        int kh[KH];
+#pragma unroll
+        for (int i = 0; i < KH; ++i) kh[i] = i < cnt ? pm[beg + i] : 0;
+        for (int64_t rhs0 = 0; rhs0 < a.n_rhs; rhs0 += RB) {
+            const int nr = (int)min((int64_t)RB, a.n_rhs - rhs0);
+            const cx<T>* cr = coeffs + rhs0 * a.n;
+            cx<T> acc[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) acc[q] = {(T)0, (T)0};
+#pragma unroll
+            for (int i = 0; i < KH; ++i) {
+                if (i < cnt) {
+                    cx<T> v[RB];
+#pragma unroll
+                    for (int q = 0; q < RB; ++q)
+                        if (q < nr) v[q] = cr[q * a.n + kh[i]];
+#pragma unroll
+                    for (int q = 0; q < RB; ++q)
+                        if (q < nr) acc[q] = acc[q] + v[q];
                 }
-                ks[q] = k;
             }
+            for (int i = KH; i < cnt; ++i) {
+                const int k = pm[beg + i];
+                cx<T> v[RB];
+#pragma unroll
+                for (int q = 0; q < RB; ++q)
+                    if (q < nr) v[q] = cr[q * a.n + k];
+#pragma unroll
+                for (int q = 0; q < RB; ++q)
+                    if (q < nr) acc[q] = acc[q] + v[q];
+            }
+            cx<T>* wr = work + rhs0 * a.work_stride + D.work_off + m;
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (q < nr) wr[q * a.work_stride] = acc[q];
         }
-        for (int64_t rhs = 0; rhs < a.n_rhs; ++rhs) {
-            const cx<T>* cr = coeffs + rhs * a.n;
-            cx<T> acc = {(T)0, (T)0};
-            if (cnt <= kBinSort) {
-                for (int i = 0; i < cnt; ++i) acc = acc + cr[ks[i]];
+    }
+}
+
+// ---- right-hand-side interleaving ------------------------------------------------------------------
+// With several right-hand sides, the gather's random bin reads and the bin sums' random coefficient
+// reads would fetch one line per right-hand side.  A block of RB right-hand sides is first copied
+// into 64-byte slots (RB values of one bin, or of one coefficient, side by side; coalesced on both
+// sides), so that one random access fetches the whole block in one line.  The sums run in the same
+// order as in the plain kernels, so the results are bit-identical.
+template <typename T>
+struct alignas(64) RhsSlot {
+    static constexpr int RB = 64 / (int)sizeof(cx<T>);
+    cx<T> v[RB];
+};
+
+// bins m < M_l of lattice blockIdx.y, right-hand sides [0, nr) of work -> slot samp_off_l + m
+template <typename T>
+__global__ __launch_bounds__(256) void k_bins_ilv(TxArgs a, const cx<T>* __restrict__ work, RhsSlot<T>* out, int nr) {
+    const LatDesc D = a.desc[blockIdx.y];
+    if (a.tx[D.tx].in_block) return;   // written by the persistent small-transform kernel
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < D.M; m += (int64_t)gridDim.x * blockDim.x) {
+        RhsSlot<T> v;
+#pragma unroll
+        for (int q = 0; q < RhsSlot<T>::RB; ++q)
+            v.v[q] = q < nr ? work[q * a.work_stride + D.work_off + m] : cx<T>{(T)0, (T)0};
+        out[D.samp_off + m] = v;
+    }
+}
+
+// coefficients g < n, right-hand sides [0, nr) -> slot g
+template <typename T>
+__global__ __launch_bounds__(256) void k_coef_ilv(TxArgs a, const cx<T>* __restrict__ coeffs, RhsSlot<T>* out, int nr) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        RhsSlot<T> v;
+#pragma unroll
+        for (int q = 0; q < RhsSlot<T>::RB; ++q) v.v[q] = q < nr ? coeffs[q * a.n + g] : cx<T>{(T)0, (T)0};
+        out[g] = v;
+    }
+}
+
+// k_gather over interleaved bins: one thread per frequency, nr <= RB right-hand sides
+template <typename T, bool EVAL, bool SINGLE>
+__global__ __launch_bounds__(256) void k_gather_ilv(TxArgs a, const RhsSlot<T>* __restrict__ bins, cx<T>* coeffs,
+                                                    int nr) {
+    constexpr int RB = RhsSlot<T>::RB;
+    constexpr int LC = 4;   // lattice slots in flight
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < a.n; g += (int64_t)gridDim.x * blockDim.x) {
+        const TxDesc t = get_tx<SINGLE>(a, g);
+        if (t.in_block) continue;
+        cx<T> acc[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[q] = {(T)0, (T)0};
+        int cnt = 0;
+        for (int j0 = 0; j0 < t.nlat; j0 += LC) {
+            int32_t r[LC];
+            uint32_t use;
+            if (EVAL) {
+#pragma unroll
+                for (int u = 0; u < LC; ++u) r[u] = a.res32[(int64_t)min(j0 + u, t.nlat - 1) * a.rs + g];
+                use = (t.nlat - j0 >= LC) ? (uint32_t)((1u << LC) - 1) : ((1u << (t.nlat - j0)) - 1u);
             } else {
-                for (int i = beg; i < end; ++i) acc = acc + cr[pm[i]];
+                use = unaliased_chunk<LC>(a, t, j0, g, r);
+                cnt += __popc(use);
             }
-            work[rhs * a.work_stride + D.work_off + m] = acc;
+            RhsSlot<T> v[LC];
+#pragma unroll
+            for (int u = 0; u < LC; ++u)
+                if ((use >> u) & 1u) v[u] = bins[a.desc[t.lat0 + j0 + u].samp_off + r[u]];
+#pragma unroll
+            for (int u = 0; u < LC; ++u)   // ascending l
+                if ((use >> u) & 1u) {
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) acc[q] = acc[q] + v[u].v[q];
+                }
         }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            if (q < nr) {
+                cx<T> v = acc[q];
+                if (!EVAL) v = cnt ? cx<T>{v.x / (T)cnt, v.y / (T)cnt} : cx<T>{(T)0, (T)0};
+                coeffs[q * a.n + g] = v;
+            }
+        }
+    }
+}
+
+// k_bin_sum over interleaved coefficients: one thread per bin, nr <= RB right-hand sides
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_sum_ilv(TxArgs a, const RhsSlot<T>* __restrict__ cs, cx<T>* work, int nr) {
+    constexpr int RB = RhsSlot<T>::RB;
+    const int l = blockIdx.y;
+    const LatDesc D = a.desc[l];
+    const TxDesc t = a.tx[D.tx];
+    const int j = l - t.lat0;
+    const int base = bin_offset(a, D.samp_off);
+    const int32_t* pm = a.perm + (int64_t)j * a.rs + t.foff;
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < D.M; m += (int64_t)gridDim.x * blockDim.x) {
+        const int beg = bin_offset(a, D.samp_off + m) - base;
+        const int end = m + 1 < D.M ? bin_offset(a, D.samp_off + m + 1) - base : (int)t.fn;
+        const int cnt = end - beg;
+        cx<T> acc[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) acc[q] = {(T)0, (T)0};
+        for (int i0 = 0; i0 < cnt; i0 += 2) {   // two slots in flight
+            RhsSlot<T> v[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (i0 + u < cnt) v[u] = cs[pm[beg + i0 + u]];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (i0 + u < cnt) {
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) acc[q] = acc[q] + v[u].v[q];
+                }
+        }
+        cx<T>* wr = work + D.work_off + m;
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (q < nr) wr[q * a.work_stride] = acc[q];
     }
 }
 
@@ -763,6 +949,22 @@ template <typename T>
 void launch_gather(const TxArgs& a, const cx<T>* work, cx<T>* coeffs, bool eval, hipStream_t s) {
     if (a.n == 0 || a.n_rhs == 0) return;
     const bool single = a.ntx == 1;
+    if (a.n_rhs > 1 && a.ilv_bins) {
+        constexpr int RB = RhsSlot<T>::RB;
+        RhsSlot<T>* buf = (RhsSlot<T>*)a.ilv;
+        for (int64_t r0 = 0; r0 < a.n_rhs; r0 += RB) {
+            const int nr = (int)std::min<int64_t>(RB, a.n_rhs - r0);
+            hipLaunchKernelGGL((k_bins_ilv<T>), dim3(grid_for(a.max_M, 256, 65535), (unsigned)a.L), dim3(256), 0, s, a,
+                               work + r0 * a.work_stride, buf, nr);
+            cx<T>* cr = coeffs + r0 * a.n;
+            const dim3 grid(grid_for(a.n));
+            if (eval && single) hipLaunchKernelGGL((k_gather_ilv<T, true, true>), grid, dim3(256), 0, s, a, buf, cr, nr);
+            else if (eval) hipLaunchKernelGGL((k_gather_ilv<T, true, false>), grid, dim3(256), 0, s, a, buf, cr, nr);
+            else if (single) hipLaunchKernelGGL((k_gather_ilv<T, false, true>), grid, dim3(256), 0, s, a, buf, cr, nr);
+            else hipLaunchKernelGGL((k_gather_ilv<T, false, false>), grid, dim3(256), 0, s, a, buf, cr, nr);
+        }
+        return;
+    }
     auto go = [&](auto RBc) {
         constexpr int RB = decltype(RBc)::value;
         const dim3 grid(grid_for(a.n), (unsigned)((a.n_rhs + RB - 1) / RB));
@@ -818,13 +1020,27 @@ void launch_bin_sort(const TxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_scan_bases, dim3(1), dim3(1024), 0, s, a, nchunks);
     if (a.ntx == 1) hipLaunchKernelGGL((k_bin_place<true>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_bin_place<false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bin_order, dim3(grid_for(a.max_M, 256, 65535), (unsigned)a.L), dim3(256), 0, s, a);
 }
 
 template <typename T>
 void launch_bin_sum(const TxArgs& a, const cx<T>* coeffs, cx<T>* work, hipStream_t s) {
     if (a.L == 0 || a.n_rhs == 0) return;
-    hipLaunchKernelGGL((k_bin_sum<T>), dim3(grid_for(a.max_M, 256, 65535), (unsigned)a.L), dim3(256), 0, s, a, coeffs,
-                       work);
+    const dim3 grid(grid_for(a.max_M, 256, 65535), (unsigned)a.L);
+    if (a.n_rhs > 1 && a.ilv_coef) {
+        constexpr int RB = RhsSlot<T>::RB;
+        RhsSlot<T>* buf = (RhsSlot<T>*)a.ilv;
+        for (int64_t r0 = 0; r0 < a.n_rhs; r0 += RB) {
+            const int nr = (int)std::min<int64_t>(RB, a.n_rhs - r0);
+            if (a.n > 0)
+                hipLaunchKernelGGL((k_coef_ilv<T>), dim3(grid_for(a.n)), dim3(256), 0, s, a, coeffs + r0 * a.n, buf, nr);
+            hipLaunchKernelGGL((k_bin_sum_ilv<T>), grid, dim3(256), 0, s, a, buf, work + r0 * a.work_stride, nr);
+        }
+        return;
+    }
+    if (a.n_rhs == 1) hipLaunchKernelGGL((k_bin_sum<T, 1>), grid, dim3(256), 0, s, a, coeffs, work);
+    else if (a.n_rhs <= 4) hipLaunchKernelGGL((k_bin_sum<T, 4>), grid, dim3(256), 0, s, a, coeffs, work);
+    else hipLaunchKernelGGL((k_bin_sum<T, 8>), grid, dim3(256), 0, s, a, coeffs, work);
 }
 template void launch_bin_sum<float>(const TxArgs&, const cx<float>*, cx<float>*, hipStream_t);
 template void launch_bin_sum<double>(const TxArgs&, const cx<double>*, cx<double>*, hipStream_t);

@@ -119,6 +119,10 @@ int64_t work_limit_bytes();
 // Whether batched plans run their small transforms in the persistent in-block kernel
 // (process-wide, mr1l_batch_inblock; default on).
 bool batch_inblock_enabled();
+// Right-hand-side interleaving of the gather and the bin sums (process-wide, mr1l_rhs_interleave):
+// 0 never, 1 where the pass's random reads leave the caches (default), 2 for every pass of
+// several right-hand sides.
+int rhs_interleave_mode();
 
 // Description of the transforms a plan holds.  A plain plan has one transform; a batched plan
 // stacks several independent ones (own frequencies, own lattices).
@@ -165,7 +169,8 @@ struct Plan {
     int64_t work_stride = 0;
     int64_t filt_total = 0;
     int64_t bm_total = 0;
-    DevMem freqs, desc, tx, tx_foff, z, z32, bitmaps, filt, work, grp_lat, res32, hist, rtiles, part, bcnt, bloc, bbase, perm;
+    DevMem freqs, desc, tx, tx_foff, z, z32, bitmaps, filt, work, grp_lat, res32, hist, rtiles, part, bcnt, bloc, bbase, perm,
+        ilv;
     DevMem lsq_part;                   // block partials of mr1l_lsq_residual (allocated on first use)
     std::vector<FftGroup> groups;   // lattices grouped by Bluestein length (filter construction)
     std::vector<FftGroup> sweep;    // the same without the lattices of in-block transforms

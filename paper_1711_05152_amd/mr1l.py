@@ -65,6 +65,15 @@ def fft_smooth(mode: int = -1) -> int:
     return int(out.value)
 
 
+def rhs_interleave(mode: int = -1) -> int:
+    """mr1l_rhs_interleave: whether plans created from now on read several right-hand sides per
+    random access in the gather and the Fourier-matrix adjoint (1 by size, 2 every pass of several
+    right-hand sides, 0 never, < 0 query); returns the mode."""
+    out = C.c_int(0)
+    check(lib().mr1l_rhs_interleave(int(mode), C.byref(out)), "mr1l_rhs_interleave")
+    return int(out.value)
+
+
 class Plan:
     """mr1l_plan: frequency set I (int [n, d]), lattices (M [L], z [L, d])."""
 
