@@ -711,12 +711,50 @@ struct GroupFork {
     }
 };
 
+// A group's stage pipeline runs in pieces (a lattice range times a right-hand-side range) whose
+// Bluestein work regions together stay within a share of the 256 MB Infinity Cache, so that stage
+// 2 reads what stage 1 wrote, and stage 3 what stage 2 wrote, from there instead of from HBM.
+// Groups whose regions fit anyway run as one piece.
+constexpr int64_t kPieceCacheBytes = (int64_t)192 << 20;
+struct Piece {
+    int l0, nl;
+    int64_t q0, nq;
+};
+template <typename T>
+static void group_pieces(const FftGroup& g, int64_t nrhs, int conc, std::vector<Piece>& out) {
+    out.clear();
+    const int64_t region = ((int64_t)(g.n3 ? 3 : 1) << g.lgN) * (int64_t)sizeof(cx<T>);
+    const int64_t k = std::max<int64_t>(1, kPieceCacheBytes / std::max(1, conc) / region);   // regions per piece
+    if ((int64_t)g.nlat * nrhs <= 2 * k) {
+        out.push_back(Piece{0, g.nlat, 0, nrhs});
+        return;
+    }
+    if (nrhs >= k) {   // one lattice, its right-hand sides in even parts of at most k
+        const int64_t parts = (nrhs + k - 1) / k, per = (nrhs + parts - 1) / parts;
+        for (int l = 0; l < g.nlat; ++l)
+            for (int64_t q = 0; q < nrhs; q += per) out.push_back(Piece{l, 1, q, std::min(per, nrhs - q)});
+    } else {           // every right-hand side, lattices in even parts of at most k / nrhs
+        const int most = (int)std::max<int64_t>(1, k / nrhs);
+        const int parts = (g.nlat + most - 1) / most, per = (g.nlat + parts - 1) / parts;
+        for (int l = 0; l < g.nlat; l += per) out.push_back(Piece{l, std::min(per, g.nlat - l), 0, nrhs});
+    }
+}
+
+// stage pipelines running at once: the caller's stream plus the group streams in use
+static int concurrent_pipelines(const Plan* p, const GroupFork& gf) {
+    if (!gf.on) return 1;
+    int n4 = 0;
+    for (const FftGroup& g : p->sweep) n4 += !g.small;
+    return std::max(1, std::min(n4, (int)p->gstream.size() + 1));
+}
+
 template <typename T>
 static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
     const bool eval = p->weights == MR1L_W_EVAL;
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
+    std::vector<Piece> pieces;
     // small transforms of a batch, whole, in one persistent launch on the side stream, beside the
     // stage sweep of the others (they share no data)
     MR1L_HIP_TRY(inblock_begin<T>(p, y, c, true, s));
@@ -737,15 +775,25 @@ static mr1l_status forward_t(Plan* p, const cx<T>* y, cx<T>* c, hipStream_t s) {
                 continue;
             }
             const hipStream_t gs = gf.next();
-            tm.begin(2);
-            launch_p1<T>(a, g, yc, a.samp_stride, true, work, -1, false, gs);
-            tm.end();
-            tm.begin(3);
-            launch_p2<T>(a, g, work, filt, -1, yc, nullptr, gs);
-            tm.end();
-            tm.begin(4);
-            launch_p3<T>(a, g, work, work, a.work_stride, false, -1, !eval, gs);
-            tm.end();
+            group_pieces<T>(g, a.n_rhs, concurrent_pipelines(p, gf), pieces);
+            for (const Piece& pc : pieces) {
+                TxArgs b = a;
+                b.n_rhs = pc.nq;
+                FftGroup h = g;
+                h.lat = g.lat + pc.l0;
+                h.nlat = pc.nl;
+                const cx<T>* yq = yc + pc.q0 * a.samp_stride;
+                cx<T>* wq = work + pc.q0 * a.work_stride;
+                tm.begin(2);
+                launch_p1<T>(b, h, yq, a.samp_stride, true, wq, -1, false, gs);
+                tm.end();
+                tm.begin(3);
+                launch_p2<T>(b, h, wq, filt, -1, yq, nullptr, gs);
+                tm.end();
+                tm.begin(4);
+                launch_p3<T>(b, h, wq, wq, a.work_stride, false, -1, !eval, gs);
+                tm.end();
+            }
         }
         MR1L_HIP_TRY(gf.end());
         tm.begin(5);
@@ -763,6 +811,7 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
     cx<T>* work = p->work.as<cx<T>>();
     const cx<T>* filt = (const cx<T>*)p->filt_ptr;
     StageTimer tm(p, s);
+    std::vector<Piece> pieces;
     MR1L_HIP_TRY(inblock_begin<T>(p, c, y, false, s));
     index_pass(p, eval, tm, s);
     if (eval && p->args.bsort && !(p->cache_alias && p->sort_valid)) {
@@ -795,15 +844,25 @@ static mr1l_status adjoint_t(Plan* p, const cx<T>* c, cx<T>* y, hipStream_t s) {
                 continue;
             }
             const hipStream_t gs = gf.next();
-            tm.begin(2);
-            launch_p1<T>(a, g, work, a.work_stride, false, work, +1, !eval, gs);
-            tm.end();
-            tm.begin(3);
-            launch_p2<T>(a, g, work, filt, +1, nullptr, yc, gs);
-            tm.end();
-            tm.begin(4);
-            launch_p3<T>(a, g, work, yc, a.samp_stride, true, +1, !eval, gs);
-            tm.end();
+            group_pieces<T>(g, a.n_rhs, concurrent_pipelines(p, gf), pieces);
+            for (const Piece& pc : pieces) {
+                TxArgs b = a;
+                b.n_rhs = pc.nq;
+                FftGroup h = g;
+                h.lat = g.lat + pc.l0;
+                h.nlat = pc.nl;
+                cx<T>* yq = yc + pc.q0 * a.samp_stride;
+                cx<T>* wq = work + pc.q0 * a.work_stride;
+                tm.begin(2);
+                launch_p1<T>(b, h, wq, a.work_stride, false, wq, +1, !eval, gs);
+                tm.end();
+                tm.begin(3);
+                launch_p2<T>(b, h, wq, filt, +1, nullptr, yq, gs);
+                tm.end();
+                tm.begin(4);
+                launch_p3<T>(b, h, wq, yq, a.samp_stride, true, +1, !eval, gs);
+                tm.end();
+            }
         }
         MR1L_HIP_TRY(gf.end());
     }
