@@ -216,7 +216,25 @@ struct ColTile {
     static constexpr int TLG = WANT < kTileLg ? kTileLg : (WANT > MAX_LG ? MAX_LG : WANT);
     static constexpr int LGC = TLG - LGN1, C = 1 << LGC;
     static constexpr int NT = (1 << TLG) / 16;                     // threads: 16 values each
+    // tiles whose row pieces make up one 128-byte line (1 while a tile's rows are whole lines)
+    static constexpr int G = LGC < LINE_LG ? (1 << (LINE_LG - LGC)) : 1;
 };
+
+// Tile of workgroup b (of nb).  Workgroups are dispatched to the eight XCDs in turn, so b, b + 8,
+// ..., b + 8 (G - 1) share an XCD and start close together: they take the G tiles whose row pieces
+// share 128-byte lines, which each XCD's L2 then fetches once.  A permutation of the tiles (the
+// last nb mod 8G workgroups keep their own index).
+template <int G>
+__device__ __forceinline__ int line_tile(int b, int nb) {
+    if constexpr (G == 1) {
+        return b;
+    } else {
+        const int full = nb / (8 * G) * (8 * G);
+        if (b >= full) return b;
+        const int r = b % (8 * G);
+        return (b - r) + (r % 8) * G + r / 8;
+    }
+}
 
 template <typename T, int LGN, int LG1>
 struct Rot {
@@ -530,8 +548,9 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p1(TxArgs a, con
     __shared__ cx<T> ph[PhaseTab<T>::n];
     phase_fill<T>(ph);
     __syncthreads();
-    const int li = blockIdx.x / TPL;
-    const int c0 = (blockIdx.x - li * TPL) << LGC;
+    const int tb = line_tile<CT::G>((int)blockIdx.x, (int)gridDim.x);
+    const int li = tb / TPL;
+    const int c0 = (tb - li * TPL) << LGC;
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     const cx<T>* in = src + rhs * src_stride + (SRC == 0 ? D.samp_off : D.work_off);
@@ -828,8 +847,9 @@ __global__ __launch_bounds__((ColTile<T, LGN, LG1>::NT)) void k_p3(TxArgs a, con
     __shared__ cx<T> ph[PhaseTab<T>::n];
     phase_fill<T>(ph);
     __syncthreads();
-    const int li = blockIdx.x / TPL;
-    const int c0 = (blockIdx.x - li * TPL) << LGC;
+    const int tb = line_tile<CT::G>((int)blockIdx.x, (int)gridDim.x);
+    const int li = tb / TPL;
+    const int c0 = (tb - li * TPL) << LGC;
     const LatDesc D = a.desc[lat[li]];
     const int64_t rhs = blockIdx.y;
     cx<T>* w = work + rhs * a.work_stride + D.work_off;
