@@ -4,7 +4,7 @@
 #pragma once
 #include <stdint.h>
 static const int8_t kTunedSplit[2][25] = {
-    {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 7, 8, -1, -1, -1, -1, -1, -1, 10, -1, -1, -1},
+    {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 7, 8, 8, -1, -1, -1, -1, -1, -1, -1, -1, -1},
     {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 7, 8, 8, -1, -1, -1, -1, -1, -1, -1, -1, -1},
 };
 // Stage-2 variants (bit 0: radix schedule of orders 3 / 2; bit 1: 4096-element row tiles; bit 2:
@@ -12,11 +12,11 @@ static const int8_t kTunedSplit[2][25] = {
 // -1 keeps variant 0.
 static const int8_t kTunedP2[2][25] = {
     {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 6, 6, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
-    {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 6, 6, -1, 4, 4, 4, -1, -1, -1, -1, -1, -1},
+    {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 6, 6, -1, -1, 4, -1, -1, -1, -1, -1, -1, -1},
 };
 // Bluestein length classes 2^lg whose lattices take 3 * 2^(lg - 2) when all of them fit, chosen by
 // the same tuner (1: the factor-3 length measured faster; 0 or -1: powers of two).
 static const int8_t kTunedSmooth[2][25] = {
     {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
-    {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 1, 1, 1, -1, 1, 1},
+    {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, 1, 1, 1, 1, -1, 1, 1},
 };
