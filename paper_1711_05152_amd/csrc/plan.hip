@@ -714,7 +714,9 @@ struct GroupFork {
 // A group's stage pipeline runs in pieces (a lattice range times a right-hand-side range) whose
 // Bluestein work regions together stay within a share of the 256 MB Infinity Cache, so that stage
 // 2 reads what stage 1 wrote, and stage 3 what stage 2 wrote, from there instead of from HBM.
-// Groups whose regions fit anyway run as one piece.
+// Groups whose regions fit anyway run as one piece, and so do passes of one right-hand side (a
+// batch of transforms: the many short launches there slowed the eager call beside the in-block
+// kernel and gained nothing).
 constexpr int64_t kPieceCacheBytes = (int64_t)192 << 20;
 struct Piece {
     int l0, nl;
@@ -725,7 +727,7 @@ static void group_pieces(const FftGroup& g, int64_t nrhs, int conc, std::vector<
     out.clear();
     const int64_t region = ((int64_t)(g.n3 ? 3 : 1) << g.lgN) * (int64_t)sizeof(cx<T>);
     const int64_t k = std::max<int64_t>(1, kPieceCacheBytes / std::max(1, conc) / region);   // regions per piece
-    if ((int64_t)g.nlat * nrhs <= 2 * k) {
+    if (nrhs == 1 || (int64_t)g.nlat * nrhs <= 2 * k) {
         out.push_back(Piece{0, g.nlat, 0, nrhs});
         return;
     }
