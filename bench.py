@@ -478,7 +478,7 @@ def extra_autograd(steps: int):
         c.grad = None
         loss.backward()
         with torch.no_grad():
-            c.sub_(step * c.grad)
+            c.add_(c.grad, alpha=-step)   # one fused elementwise pass
         return loss.detach()
 
     losses.append(float(gd_step()))
