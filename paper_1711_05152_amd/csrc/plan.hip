@@ -526,22 +526,6 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->rhs_chunk = std::max<int64_t>(1, std::min<int64_t>(P->n_rhs, sp.max_work_bytes / per_rhs));
     }
     MR1L_HIP_TRY(P->work.alloc((size_t)std::max<int64_t>(1, P->work_stride * P->rhs_chunk) * sizeof(cx<T>)));
-    // right-hand-side interleaving for the gather and the bin sums of passes with several
-    // right-hand sides: 64 bytes per bin or coefficient, within the work-area bound
-    P->args.ilv = nullptr;
-    P->args.ilv_bins = P->args.ilv_coef = false;
-    {
-        const int mode = rhs_interleave_mode();
-        const int64_t pass = P->rhs_chunk * (int64_t)sizeof(cx<T>);
-        if (mode > 0 && P->rhs_chunk > 1 && std::max<int64_t>(n, P->sum_M) <= sp.max_work_bytes / 64) {
-            P->args.ilv_bins = mode == 2 || P->sum_M * pass >= kIlvBinBytes;
-            P->args.ilv_coef = sp.weights == MR1L_W_EVAL && (mode == 2 || (int64_t)n * pass >= kIlvCoefBytes);
-        }
-        if (P->args.ilv_bins || P->args.ilv_coef) {
-            MR1L_HIP_TRY(P->ilv.alloc((size_t)std::max<int64_t>(n, P->sum_M) * 64));
-            P->args.ilv = P->ilv.p;
-        }
-    }
     // Fourier-matrix adjoint by counting sort: every bin is summed by one thread in ascending k,
     // so the synthesis is bit-reproducible from run to run (floating-point atomics are kept only for
     // plans beyond the sort's 32-bit positions)
@@ -558,6 +542,22 @@ static mr1l_status plan_create_t(const PlanSpec& sp, Plan** out) {
         P->args.bloc = P->bloc.as<int32_t>();
         P->args.bbase = P->bbase.as<int32_t>();
         P->args.perm = P->perm.as<int32_t>();
+    }
+    // right-hand-side interleaving for the gather and the bin sums of passes with several
+    // right-hand sides: 64 bytes per bin or coefficient, within the work-area bound
+    P->args.ilv = nullptr;
+    P->args.ilv_bins = P->args.ilv_coef = false;
+    {
+        const int mode = rhs_interleave_mode();
+        const int64_t pass = P->rhs_chunk * (int64_t)sizeof(cx<T>);
+        if (mode > 0 && P->rhs_chunk > 1 && std::max<int64_t>(n, P->sum_M) <= sp.max_work_bytes / 64) {
+            P->args.ilv_bins = mode == 2 || P->sum_M * pass >= kIlvBinBytes;
+            P->args.ilv_coef = P->args.bsort && (mode == 2 || (int64_t)n * pass >= kIlvCoefBytes);
+        }
+        if (P->args.ilv_bins || P->args.ilv_coef) {
+            MR1L_HIP_TRY(P->ilv.alloc((size_t)std::max<int64_t>(n, P->sum_M) * 64));
+            P->args.ilv = P->ilv.p;
+        }
     }
     P->args.nbins = P->sum_M;
     P->args.max_M = maxM;
